@@ -1,0 +1,179 @@
+/*
+ * gls.h - C ABI of the MI355X solver for sequences of generalized
+ * least-squares problems (Fabregat-Traver, Aulchenko, Bientinesi,
+ * "Solving Sequences of Generalized Least-Squares Problems on
+ * Multi-threaded Architectures").
+ *
+ * The library computes, for i = 1..m (Sec. 1, Eq. (1)),
+ *
+ *     b_i = (X_i^T M^{-1} X_i)^{-1} X_i^T M^{-1} y,   X_i = (X_L | X_{R_i}),
+ *
+ * following the structure of the paper's in-core algorithm (Sec. 2, the
+ * algorithm "hp-gwas"): M = L L^T is factored once, the fixed block X_L
+ * and y are whitened once, each block of genotype columns is whitened by
+ * one large triangular solve, and the small SPD systems S_i b_i = c_i of
+ * size p = p_L + p_R are assembled from the fixed and per-problem parts
+ * (Fig. 1) and solved.
+ *
+ * Conventions (all entry points):
+ *  - Every array pointer is a DEVICE pointer, column-major, owned by the
+ *    caller.  The library never writes to an input and never frees
+ *    caller memory.
+ *  - A handle (gls_handle) is opaque and owns device memory: the factor
+ *    of M in the kernels' packed layouts, the whitened fixed block and its
+ *    products, and a workspace for whitened genotype columns.
+ *  - Work is enqueued on the handle's HIP stream (hipStream_t passed as
+ *    void*; NULL = the null stream).  Unless stated otherwise a call only
+ *    enqueues work: inputs must stay alive, and outputs are valid, once
+ *    the stream has passed the call.
+ *  - Return codes: 0 success; -k argument k (1-based) invalid; positive
+ *    values are the GLS_E_* codes below.  No exception crosses the ABI.
+ *  - A handle is not thread-safe.  Distinct handles (also those made by
+ *    gls_fork) may be used concurrently on distinct streams.
+ *  - Limits: n > p (Sec. 2: X of full rank with n > p), 1 <= p_L,
+ *    1 <= p_R, p = p_L + p_R <= 20 (Sec. 1), 1 <= t <= 8 phenotypes.
+ */
+#ifndef GLS_H
+#define GLS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gls_handle_s* gls_handle;
+
+/* Arithmetic of the genotype whitening.
+ * GLS_FP64: every step in FP64.
+ * GLS_FP32_REFINE: the off-diagonal products of the triangular solve in
+ *   FP32 matrix cores (FP32 accumulation within one diagonal-block chunk,
+ *   FP64 running sum), everything else in FP64, and one FP64 refinement
+ *   step of the normal equations per problem.  Not part of the paper,
+ *   whose routines are FP64 only. */
+typedef enum { GLS_FP64 = 0, GLS_FP32_REFINE = 1 } gls_precision;
+
+enum {
+  GLS_OK = 0,
+  GLS_E_NOT_SPD = 1,     /* gls_factor: M is not positive definite        */
+  GLS_E_STATE = 2,       /* call out of order (e.g. solve before whiten)  */
+  GLS_E_OOM = 3,         /* device allocation failed                      */
+  GLS_E_HIP = 4,         /* a HIP runtime call failed                     */
+  GLS_E_UNSUPPORTED = 5  /* valid but unsupported request                 */
+};
+
+/* Factor M = L L^T (Cholesky; the potrf of Alg. 3-5, done once per
+ * cohort).  M: n x n SPD, leading dimension ldm >= n; only its lower
+ * triangle is read.  prec: a gls_precision value.  stream: hipStream_t or
+ * NULL.  On success *out receives a new handle bound to `stream`.
+ * SYNCHRONOUS: returns after the factorization has finished, so M may be
+ * freed on return.  If M is not positive definite the return value is
+ * GLS_E_NOT_SPD, *out still receives a handle (to be released with
+ * gls_free) and gls_last_info() gives the order of the first non-positive
+ * leading minor (LAPACK potrf convention).  Other errors leave *out NULL. */
+int gls_factor(gls_handle* out, int64_t n, const double* M, int64_t ldm,
+               int prec, void* stream);
+
+/* Whiten the fixed part once (Alg. 5, the trsm of X_L, the trsv of y, the
+ * syrk S_TL = W_L^T W_L and the gemv C_T = W_L^T ytil, with W_L = L^{-1} X_L,
+ * ytil = L^{-1} y).  X_L: n x p_L (ldx >= n); Y: n x t phenotypes sharing M
+ * (ldy >= n).  intercept_col: index of the all-ones column of X_L, or -1;
+ * the FP32_REFINE form uses it to center genotypes exactly (it requires
+ * one, else GLS_E_UNSUPPORTED).  Asynchronous.  May be called again to
+ * replace the fixed part. */
+int gls_whiten_fixed(gls_handle h, int64_t p_L, const double* X_L, int64_t ldx,
+                     int64_t t, const double* Y, int64_t ldy,
+                     int64_t intercept_col);
+
+/* Solve one block of problems (the loop body of Alg. 5 / Alg. 8: one
+ * large trsm over the block, then per problem the gemv/dot assembly of
+ * S_i and c_i and the posv).  X_R: int8 genotypes, n x (nsnp*p_R),
+ * ldxr >= n; problem i owns columns i*p_R .. i*p_R+p_R-1.
+ * B: output, element (r, j, i) = component r of b_i for phenotype j at
+ * B[(i*t + j)*ldb + r], ldb >= p, components ordered (b_L; b_R) like the
+ * columns of X_i.  info: int32[nsnp] or NULL; info[i] = 0, or k > 0 if the
+ * k-th leading minor of S_i is not positive (X_i rank deficient), in which
+ * case b_i is set to NaN.  Asynchronous; needs gls_whiten_fixed first.
+ * The workspace grows (synchronously) when a block is larger than any
+ * before; gls_reserve avoids that inside a timed or captured loop. */
+int gls_solve_block(gls_handle h, int64_t nsnp, int64_t p_R,
+                    const int8_t* X_R, int64_t ldxr, double* B, int64_t ldb,
+                    int32_t* info);
+
+/* Pre-size the workspace for blocks of up to max_cols = nsnp*p_R genotype
+ * columns.  Synchronous allocation. */
+int gls_reserve(gls_handle h, int64_t max_cols);
+
+/* Release the handle and all device memory it owns (after synchronizing
+ * its stream).  NULL is ignored.  A factor shared with forked handles is
+ * released with the last of them. */
+void gls_free(gls_handle h);
+
+/* A new handle that shares h's factor and fixed part (read-only) but has
+ * its own workspace and is bound to `stream`, so blocks can be solved
+ * concurrently on several streams.  The fixed part must have been set on
+ * h before forking.  Synchronizes h's stream once. */
+int gls_fork(gls_handle h, void* stream, gls_handle* out);
+
+/* Rebind h to another stream (ordering with the old stream is the
+ * caller's business). */
+int gls_set_stream(gls_handle h, void* stream);
+
+/* Device bytes a handle holds for a cohort of n individuals, p_L fixed
+ * columns, t phenotypes and blocks of up to max_cols genotype columns in
+ * precision prec (factor, fixed part and workspace; the transient buffer
+ * of gls_factor is counted too).  Used for admission by memory footprint. */
+size_t gls_footprint_bytes(int64_t n, int64_t p_L, int64_t t, int64_t max_cols,
+                           int prec);
+
+/* Order of the first non-positive leading minor found by gls_factor, 0 if
+ * none.  Returns -1 for a NULL handle. */
+int gls_last_info(gls_handle h);
+
+/* Static description of a return code. */
+const char* gls_strerror(int code);
+
+/* ---- inspection ------------------------------------------------------- */
+
+/* Copy L (lower triangle; the strict upper triangle is set to zero) into
+ * the caller's n x n device array (ldl >= n).  Asynchronous. */
+int gls_copy_factor(gls_handle h, double* L, int64_t ldl);
+
+/* Copy the whitened fixed part: WL n x p_L (ldwl >= n), Yt n x t
+ * (ldyt >= n), S_TL p_L x p_L and C_T p_L x t (both packed, ld = p_L).
+ * Any pointer may be NULL.  Asynchronous. */
+int gls_copy_fixed(gls_handle h, double* WL, int64_t ldwl, double* Yt,
+                   int64_t ldyt, double* S_TL, double* C_T);
+
+/* W = L^{-1} X for int8 X (n x ncols, ldx >= n), written to the caller's
+ * n x ncols FP64 array (ldw >= n): the genotype whitening step on its own
+ * (Alg. 5, the trsm of the X_R block), in the handle's precision.
+ * Asynchronous. */
+int gls_whiten_block(gls_handle h, int64_t ncols, const int8_t* X, int64_t ldx,
+                     double* W, int64_t ldw);
+
+/* ---- several cohorts in one launch (serving) ----------------------------
+ * One work item per block of problems of one handle.  All items are
+ * whitened by one launch of the triangular-solve kernel and assembled and
+ * solved by one more, on `stream` (not the handles' own streams; the
+ * caller orders them).  Each item needs its own handle (or fork), because
+ * the item uses the handle's workspace.  Results equal gls_solve_block's
+ * for the same item bit for bit. */
+typedef struct {
+  gls_handle h;
+  int64_t nsnp;
+  int64_t p_R;
+  const int8_t* X_R;
+  int64_t ldxr;
+  double* B;
+  int64_t ldb;
+  int32_t* info;
+} gls_work;
+
+int gls_solve_multi(const gls_work* items, int64_t count, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GLS_H */

@@ -1,0 +1,72 @@
+"""Builds the native libraries in-tree.
+
+  libgls.so     the solver (HIP kernels for gfx950 + the C ABI of include/gls.h)
+  libglsgen.so  the synthetic-input generator (host C, OpenMP)
+
+Run `python -m paper_1210_7325_amd.build` or call build_all().
+"""
+from __future__ import annotations
+
+import os
+import shutil
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+BUILD = os.path.join(ROOT, "_build")
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ARCH = "gfx950"
+HIP_FLAGS = [
+    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+    # keep MFMA accumulators in VGPRs (no AGPR round trips in the loops)
+    "-mllvm", "-amdgpu-mfma-vgpr-form=1",
+    # never emit packed FP32 arithmetic
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    f"-I{INCLUDE}", f"-I{CSRC}",
+]
+
+
+def _run(cmd):
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    out = "\n".join(l for l in r.stdout.splitlines() if "packed-fp32-ops" not in l)
+    if r.returncode != 0:
+        sys.stderr.write(out + "\n")
+        raise RuntimeError(f"build step failed: {' '.join(cmd)}")
+    return out
+
+
+def build_gls(verbose: bool = False) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    objs = []
+    for src, lang in (("gls_kernels.hip", "hip"), ("gls_api.cpp", "hip")):
+        obj = os.path.join(BUILD, src + ".o")
+        _run([HIPCC, "-x", lang, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
+        objs.append(obj)
+    tmp = os.path.join(PKG, "libgls.so.tmp")
+    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp])
+    os.replace(tmp, os.path.join(PKG, "libgls.so"))
+    return os.path.join(PKG, "libgls.so")
+
+
+def build_gen() -> str:
+    out = os.path.join(PKG, "libglsgen.so")
+    cc = shutil.which("gcc") or "cc"
+    tmp = out + ".tmp"
+    _run([cc, "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
+          os.path.join(CSRC, "datagen.c"), "-o", tmp])
+    os.replace(tmp, out)
+    return out
+
+
+def build_all() -> None:
+    build_gen()
+    build_gls()
+
+
+if __name__ == "__main__":
+    build_all()
+    print("built", os.path.join(PKG, "libgls.so"), os.path.join(PKG, "libglsgen.so"))

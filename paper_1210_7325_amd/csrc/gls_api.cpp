@@ -1,0 +1,436 @@
+// Host side of the C ABI declared in include/gls.h: argument checks,
+// device memory ownership, stream ordering and kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+#include "gls.h"
+#include "gls_internal.h"
+
+using namespace gls;
+
+namespace {
+
+struct Cohort {
+  std::atomic<int> refs{1};
+  int64_t n = 0, n_pad = 0;
+  int K = 0;
+  int prec = GLS_FP64;
+  int info = 0;
+  double* Lstrips = nullptr;   // off-diagonal strips, fragment layout
+  double* LinvP = nullptr;     // inverted diagonal blocks, fragment layout
+  double* Ldiag = nullptr;     // diagonal blocks of L, column-major NB x NB
+  float* Lstrips32 = nullptr;  // FP32 copy of the strips (FP32_REFINE)
+  // fixed part
+  bool fixed = false;
+  int64_t pL = 0, t = 0, icol = -1;
+  double* Xfix = nullptr;      // [X_L | Y] column-major n x (pL+t)
+  double* Wfix = nullptr;      // L^{-1}[X_L | Y], slab layout (one slab)
+  double* F = nullptr;         // row-major n_pad x (pL+t)
+  double* STL = nullptr;       // pL x pL
+  double* CT = nullptr;        // pL x t
+};
+
+}  // namespace
+
+struct gls_handle_s {
+  Cohort* c = nullptr;
+  hipStream_t stream = nullptr;
+  double* W = nullptr;         // workspace: whitened genotype columns, slab layout
+  int64_t Wcols = 0;           // capacity in columns (multiple of TRSM_C)
+};
+
+namespace {
+
+int hip_code(hipError_t e) {
+  if (e == hipSuccess) return GLS_OK;
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return GLS_E_OOM;
+  return GLS_E_HIP;
+}
+
+#define HIPCHK(x)                         \
+  do {                                    \
+    hipError_t e_ = (x);                  \
+    if (e_ != hipSuccess) return hip_code(e_); \
+  } while (0)
+
+template <typename T>
+int dalloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  return hip_code(hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T)));
+}
+
+template <typename T>
+void dfree(T*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+void cohort_free(Cohort* c) {
+  if (!c) return;
+  dfree(c->Lstrips);
+  dfree(c->LinvP);
+  dfree(c->Ldiag);
+  dfree(c->Lstrips32);
+  dfree(c->Xfix);
+  dfree(c->Wfix);
+  dfree(c->F);
+  dfree(c->STL);
+  dfree(c->CT);
+  delete c;
+}
+
+int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+size_t strips_count(int K) { return (size_t)K * (size_t)(K - 1) / 2 * (size_t)NB * NB; }
+
+int ensure_workspace(gls_handle h, int64_t ncols) {
+  const int64_t need = round_up(std::max<int64_t>(ncols, 1), TRSM_C);
+  if (need <= h->Wcols) return GLS_OK;
+  HIPCHK(hipStreamSynchronize(h->stream));
+  dfree(h->W);
+  h->Wcols = 0;
+  int rc = dalloc(&h->W, (size_t)h->c->n_pad * (size_t)need);
+  if (rc) return rc;
+  h->Wcols = need;
+  return GLS_OK;
+}
+
+JobDesc make_job(gls_handle h, int64_t slab0, int64_t ncols, const void* X, int64_t ldx) {
+  JobDesc j;
+  j.slab0 = slab0;
+  j.n = h->c->n;
+  j.ncols = ncols;
+  j.X = X;
+  j.ldx = ldx;
+  j.Lstrips = h->c->Lstrips;
+  j.LinvP = h->c->LinvP;
+  j.W = h->W;
+  j.K = h->c->K;
+  return j;
+}
+
+AsmDesc make_asm(gls_handle h, int64_t grp0, int64_t nsnp, int64_t pR, double* B, int64_t ldb,
+                 int32_t* info) {
+  AsmDesc a;
+  a.grp0 = grp0;
+  a.n = h->c->n;
+  a.n_pad = h->c->n_pad;
+  a.W = h->W;
+  a.F = h->c->F;
+  a.STL = h->c->STL;
+  a.CT = h->c->CT;
+  a.nsnp = nsnp;
+  a.B = B;
+  a.ldb = ldb;
+  a.info = info;
+  a.C = TRSM_C;
+  a.pL = (int)h->c->pL;
+  a.pR = (int)pR;
+  a.t = (int)h->c->t;
+  return a;
+}
+
+// Argument checks shared by gls_solve_block and gls_solve_multi; `base`
+// is the ABI position of the nsnp argument.
+int check_block(gls_handle h, int64_t nsnp, int64_t pR, const int8_t* X_R, int64_t ldxr,
+                double* B, int64_t ldb, int base) {
+  if (!h) return -(base - 1);
+  if (nsnp < 0) return -base;
+  if (!h->c->fixed) return GLS_E_STATE;
+  const int64_t p = h->c->pL + pR;
+  if (pR < 1 || pR > 16 || p > MAXP || h->c->n <= p) return -(base + 1);
+  if (nsnp > 0 && !X_R) return -(base + 2);
+  if (ldxr < h->c->n) return -(base + 3);
+  if (nsnp > 0 && !B) return -(base + 4);
+  if (ldb < p) return -(base + 5);
+  return GLS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* gls_strerror(int code) {
+  switch (code) {
+    case GLS_OK: return "success";
+    case GLS_E_NOT_SPD: return "matrix M is not positive definite";
+    case GLS_E_STATE: return "call out of order for this handle";
+    case GLS_E_OOM: return "device memory allocation failed";
+    case GLS_E_HIP: return "HIP runtime error";
+    case GLS_E_UNSUPPORTED: return "unsupported request";
+    default: return code < 0 ? "invalid argument" : "unknown error";
+  }
+}
+
+size_t gls_footprint_bytes(int64_t n, int64_t p_L, int64_t t, int64_t max_cols, int prec) {
+  if (n < 1 || p_L < 0 || t < 0 || max_cols < 0) return 0;
+  const int K = (int)((n + NB - 1) / NB);
+  const size_t n_pad = (size_t)K * NB;
+  size_t b = 0;
+  b += strips_count(K) * 8;                        // strips
+  b += 2 * (size_t)K * NB * NB * 8;                // inverted + plain diagonal blocks
+  b += n_pad * n_pad * 8 + (size_t)K * NB * NB * 8;  // factorization work (transient)
+  const size_t w = (size_t)(p_L + t);
+  b += n * w * 8 + n_pad * TRSM_C * 8 + n_pad * w * 8 + (w * w) * 8;  // fixed part
+  b += n_pad * (size_t)round_up(std::max<int64_t>(max_cols, 1), TRSM_C) * 8;  // workspace
+  if (prec == GLS_FP32_REFINE) b += strips_count(K) * 4;
+  return b;
+}
+
+int gls_factor(gls_handle* out, int64_t n, const double* M, int64_t ldm, int prec, void* stream) {
+  if (!out) return -1;
+  *out = nullptr;
+  if (n < 2 || n > (int64_t)1 << 20) return -2;
+  if (!M) return -3;
+  if (ldm < n) return -4;
+  if (prec != GLS_FP64 && prec != GLS_FP32_REFINE) return -5;
+  if (prec == GLS_FP32_REFINE) return GLS_E_UNSUPPORTED;
+
+  Cohort* c = new (std::nothrow) Cohort();
+  if (!c) return GLS_E_OOM;
+  c->n = n;
+  c->K = (int)((n + NB - 1) / NB);
+  c->n_pad = (int64_t)c->K * NB;
+  c->prec = prec;
+  gls_handle h = new (std::nothrow) gls_handle_s();
+  if (!h) { delete c; return GLS_E_OOM; }
+  h->c = c;
+  h->stream = reinterpret_cast<hipStream_t>(stream);
+
+  double* A = nullptr;
+  double* Linv = nullptr;
+  int* dinfo = nullptr;
+  const int K = c->K;
+  const size_t blk = (size_t)K * NB * NB;
+  int rc = GLS_OK;
+  auto fail = [&](int code) {
+    dfree(A);
+    dfree(Linv);
+    dfree(dinfo);
+    cohort_free(c);
+    delete h;
+    return code;
+  };
+  if ((rc = dalloc(&A, (size_t)c->n_pad * c->n_pad))) return fail(rc);
+  if ((rc = dalloc(&Linv, blk))) return fail(rc);
+  if ((rc = dalloc(&dinfo, 1))) return fail(rc);
+  if ((rc = dalloc(&c->Ldiag, blk))) return fail(rc);
+  if ((rc = dalloc(&c->LinvP, blk))) return fail(rc);
+  if ((rc = dalloc(&c->Lstrips, std::max<size_t>(strips_count(K), 1)))) return fail(rc);
+  if (prec == GLS_FP32_REFINE && (rc = dalloc(&c->Lstrips32, std::max<size_t>(strips_count(K), 1))))
+    return fail(rc);
+
+  hipError_t e = hipMemsetAsync(dinfo, 0, sizeof(int), h->stream);
+  if (e == hipSuccess)
+    e = launch_factor(M, ldm, n, c->n_pad, K, A, c->Ldiag, Linv, c->Lstrips, c->LinvP,
+                      c->Lstrips32, dinfo, h->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(&c->info, dinfo, sizeof(int), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return fail(hip_code(e));
+  dfree(A);
+  dfree(Linv);
+  dfree(dinfo);
+  *out = h;
+  return c->info != 0 ? GLS_E_NOT_SPD : GLS_OK;
+}
+
+int gls_last_info(gls_handle h) { return h ? h->c->info : -1; }
+
+int gls_set_stream(gls_handle h, void* stream) {
+  if (!h) return -1;
+  h->stream = reinterpret_cast<hipStream_t>(stream);
+  return GLS_OK;
+}
+
+int gls_whiten_fixed(gls_handle h, int64_t p_L, const double* X_L, int64_t ldx, int64_t t,
+                     const double* Y, int64_t ldy, int64_t intercept_col) {
+  if (!h) return -1;
+  Cohort* c = h->c;
+  if (p_L < 1 || p_L > MAXP - 1 || p_L >= c->n) return -2;
+  if (!X_L) return -3;
+  if (ldx < c->n) return -4;
+  if (t < 1 || t > MAXT) return -5;
+  if (!Y) return -6;
+  if (ldy < c->n) return -7;
+  if (intercept_col < -1 || intercept_col >= p_L) return -8;
+  if (c->info != 0) return GLS_E_STATE;
+  if (c->refs.load() != 1) return GLS_E_STATE;  // shared with forks: read-only
+  if (c->prec == GLS_FP32_REFINE && intercept_col < 0) return GLS_E_UNSUPPORTED;
+
+  HIPCHK(hipStreamSynchronize(h->stream));
+  dfree(c->Xfix);
+  dfree(c->Wfix);
+  dfree(c->F);
+  dfree(c->STL);
+  dfree(c->CT);
+  c->fixed = false;
+  const int64_t w = p_L + t;
+  int rc;
+  if ((rc = dalloc(&c->Xfix, (size_t)c->n * w))) return rc;
+  if ((rc = dalloc(&c->Wfix, (size_t)c->n_pad * TRSM_C))) return rc;
+  if ((rc = dalloc(&c->F, (size_t)c->n_pad * w))) return rc;
+  if ((rc = dalloc(&c->STL, (size_t)p_L * p_L))) return rc;
+  if ((rc = dalloc(&c->CT, (size_t)p_L * t))) return rc;
+  c->pL = p_L;
+  c->t = t;
+  c->icol = intercept_col;
+
+  HIPCHK(launch_pack_fixed(X_L, ldx, Y, ldy, c->n, (int)p_L, (int)t, c->Xfix, h->stream));
+  JobTable tab;
+  tab.njobs = 1;
+  tab.j[0].slab0 = 0;
+  tab.j[0].n = c->n;
+  tab.j[0].ncols = w;
+  tab.j[0].X = c->Xfix;
+  tab.j[0].ldx = c->n;
+  tab.j[0].Lstrips = c->Lstrips;
+  tab.j[0].LinvP = c->LinvP;
+  tab.j[0].W = c->Wfix;
+  tab.j[0].K = c->K;
+  HIPCHK(launch_trsm_f64(tab, 1, h->stream));
+  HIPCHK(launch_slab_to_rowmajor(c->Wfix, c->n_pad, (int)w, c->F, h->stream));
+  HIPCHK(launch_gram(c->F, c->n, (int)p_L, (int)t, c->STL, c->CT, h->stream));
+  c->fixed = true;
+  return GLS_OK;
+}
+
+int gls_reserve(gls_handle h, int64_t max_cols) {
+  if (!h) return -1;
+  if (max_cols < 0) return -2;
+  return ensure_workspace(h, max_cols);
+}
+
+int gls_solve_block(gls_handle h, int64_t nsnp, int64_t p_R, const int8_t* X_R, int64_t ldxr,
+                    double* B, int64_t ldb, int32_t* info) {
+  int rc = check_block(h, nsnp, p_R, X_R, ldxr, B, ldb, 2);
+  if (rc) return rc;
+  if (nsnp == 0) return GLS_OK;
+  const int64_t ncols = nsnp * p_R;
+  if ((rc = ensure_workspace(h, ncols))) return rc;
+  JobTable tab;
+  tab.njobs = 1;
+  tab.j[0] = make_job(h, 0, ncols, X_R, ldxr);
+  HIPCHK(launch_trsm_i8(tab, (ncols + TRSM_C - 1) / TRSM_C, h->stream));
+  AsmTable at;
+  at.njobs = 1;
+  at.j[0] = make_asm(h, 0, nsnp, p_R, B, ldb, info);
+  const int64_t G = 16 / p_R;
+  HIPCHK(launch_assemble_solve(at, (nsnp + G - 1) / G, h->stream));
+  return GLS_OK;
+}
+
+int gls_solve_multi(const gls_work* items, int64_t count, void* stream) {
+  if (count < 0) return -2;
+  if (count == 0) return GLS_OK;
+  if (!items) return -1;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  for (int64_t i = 0; i < count; i++) {
+    const gls_work& w = items[i];
+    int rc = check_block(w.h, w.nsnp, w.p_R, w.X_R, w.ldxr, w.B, w.ldb, 2);
+    if (rc) return rc < 0 ? -1 : rc;
+    for (int64_t j = 0; j < i; j++)
+      if (items[j].h == w.h) return -1;  // each item needs its own workspace
+  }
+  for (int64_t i = 0; i < count; i++) {
+    int rc = ensure_workspace(items[i].h, items[i].nsnp * items[i].p_R);
+    if (rc) return rc;
+  }
+  for (int64_t a = 0; a < count; a += MAX_INLINE_JOBS) {
+    const int64_t b = std::min<int64_t>(count, a + MAX_INLINE_JOBS);
+    JobTable tab;
+    AsmTable at;
+    tab.njobs = at.njobs = 0;
+    int64_t slabs = 0, groups = 0;
+    for (int64_t i = a; i < b; i++) {
+      const gls_work& w = items[i];
+      if (w.nsnp == 0) continue;
+      const int64_t ncols = w.nsnp * w.p_R;
+      tab.j[tab.njobs++] = make_job(w.h, slabs, ncols, w.X_R, w.ldxr);
+      slabs += (ncols + TRSM_C - 1) / TRSM_C;
+      at.j[at.njobs++] = make_asm(w.h, groups, w.nsnp, w.p_R, w.B, w.ldb, w.info);
+      groups += (w.nsnp + 16 / w.p_R - 1) / (16 / w.p_R);
+    }
+    if (tab.njobs == 0) continue;
+    HIPCHK(launch_trsm_i8(tab, slabs, st));
+    HIPCHK(launch_assemble_solve(at, groups, st));
+  }
+  return GLS_OK;
+}
+
+int gls_fork(gls_handle h, void* stream, gls_handle* out) {
+  if (!out) return -3;
+  *out = nullptr;
+  if (!h) return -1;
+  if (!h->c->fixed) return GLS_E_STATE;
+  HIPCHK(hipStreamSynchronize(h->stream));
+  gls_handle g = new (std::nothrow) gls_handle_s();
+  if (!g) return GLS_E_OOM;
+  g->c = h->c;
+  g->c->refs.fetch_add(1);
+  g->stream = reinterpret_cast<hipStream_t>(stream);
+  *out = g;
+  return GLS_OK;
+}
+
+void gls_free(gls_handle h) {
+  if (!h) return;
+  (void)hipStreamSynchronize(h->stream);
+  dfree(h->W);
+  if (h->c->refs.fetch_sub(1) == 1) cohort_free(h->c);
+  delete h;
+}
+
+int gls_copy_factor(gls_handle h, double* L, int64_t ldl) {
+  if (!h) return -1;
+  if (!L) return -2;
+  if (ldl < h->c->n) return -3;
+  if (h->c->info != 0) return GLS_E_STATE;
+  HIPCHK(launch_unpack_factor(h->c->Lstrips, h->c->Ldiag, h->c->n, L, ldl, h->stream));
+  return GLS_OK;
+}
+
+int gls_copy_fixed(gls_handle h, double* WL, int64_t ldwl, double* Yt, int64_t ldyt, double* S_TL,
+                   double* C_T) {
+  if (!h) return -1;
+  Cohort* c = h->c;
+  if (WL && ldwl < c->n) return -3;
+  if (Yt && ldyt < c->n) return -5;
+  if (!c->fixed) return GLS_E_STATE;
+  if (WL) HIPCHK(launch_slab_to_colmajor(c->Wfix, c->n_pad, c->n, 0, c->pL, WL, ldwl, h->stream));
+  if (Yt) HIPCHK(launch_slab_to_colmajor(c->Wfix, c->n_pad, c->n, c->pL, c->t, Yt, ldyt, h->stream));
+  if (S_TL)
+    HIPCHK(hipMemcpyAsync(S_TL, c->STL, sizeof(double) * c->pL * c->pL, hipMemcpyDeviceToDevice,
+                          h->stream));
+  if (C_T)
+    HIPCHK(hipMemcpyAsync(C_T, c->CT, sizeof(double) * c->pL * c->t, hipMemcpyDeviceToDevice,
+                          h->stream));
+  return GLS_OK;
+}
+
+int gls_whiten_block(gls_handle h, int64_t ncols, const int8_t* X, int64_t ldx, double* W,
+                     int64_t ldw) {
+  if (!h) return -1;
+  if (ncols < 0) return -2;
+  if (ncols > 0 && !X) return -3;
+  if (ldx < h->c->n) return -4;
+  if (ncols > 0 && !W) return -5;
+  if (ldw < h->c->n) return -6;
+  if (h->c->info != 0) return GLS_E_STATE;
+  if (ncols == 0) return GLS_OK;
+  int rc = ensure_workspace(h, ncols);
+  if (rc) return rc;
+  JobTable tab;
+  tab.njobs = 1;
+  tab.j[0] = make_job(h, 0, ncols, X, ldx);
+  HIPCHK(launch_trsm_i8(tab, (ncols + TRSM_C - 1) / TRSM_C, h->stream));
+  HIPCHK(launch_slab_to_colmajor(h->W, h->c->n_pad, h->c->n, 0, ncols, W, ldw, h->stream));
+  return GLS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,69 @@
+// Internal declarations shared by the kernels and the host library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gls {
+
+constexpr int NB = 128;       // row block of the factorization and the solve
+constexpr int TRSM_C = 64;    // columns per slab (one work-group)
+constexpr int TRSM_WR = 4;    // waves along the rows of a block
+constexpr int TRSM_WC = 1;    // waves along the columns of a slab
+constexpr int MAXP = 20;      // p = p_L + p_R <= 20 (Sec. 1)
+constexpr int MAXT = 8;       // phenotypes per call
+constexpr int MAX_INLINE_JOBS = 16;
+
+// One block of columns of one cohort for the triangular-solve kernel.
+struct JobDesc {
+  int64_t slab0;            // first work-group of this job in the launch
+  int64_t n;                // individuals
+  int64_t ncols;            // right-hand sides
+  const void* X;            // int8 or FP64, column-major
+  int64_t ldx;
+  const double* Lstrips;    // packed off-diagonal strips of L
+  const double* LinvP;      // packed inverted diagonal blocks
+  double* W;                // output, slab layout
+  int K;                    // row blocks (n_pad / NB)
+};
+struct JobTable {
+  int njobs;
+  JobDesc j[MAX_INLINE_JOBS];
+};
+
+// One block of problems of one cohort for the assembly/solve kernel.
+struct AsmDesc {
+  int64_t grp0;             // first work-group of this job in the launch
+  int64_t n, n_pad;
+  const double* W;          // whitened genotypes, slab layout (TRSM_C)
+  const double* F;          // row-major n_pad x (pL+t): [W_L | ytil]
+  const double* STL;        // pL x pL
+  const double* CT;         // pL x t
+  int64_t nsnp;
+  double* B;
+  int64_t ldb;
+  int32_t* info;
+  int C, pL, pR, t;
+};
+struct AsmTable {
+  int njobs;
+  AsmDesc j[MAX_INLINE_JOBS];
+};
+
+hipError_t launch_factor(const double* M, int64_t ldm, int64_t n, int64_t n_pad, int K,
+                         double* A, double* Ldiag, double* Linv, double* Lstrips, double* LinvP,
+                         float* Lstrips32, int* dinfo, hipStream_t st);
+hipError_t launch_unpack_factor(const double* Lstrips, const double* Ldiag, int64_t n, double* L,
+                                int64_t ldl, hipStream_t st);
+hipError_t launch_trsm_i8(const JobTable& tab, int64_t nslabs, hipStream_t st);
+hipError_t launch_trsm_f64(const JobTable& tab, int64_t nslabs, hipStream_t st);
+hipError_t launch_pack_fixed(const double* XL, int64_t ldx, const double* Y, int64_t ldy, int64_t n,
+                             int pL, int t, double* out, hipStream_t st);
+hipError_t launch_slab_to_rowmajor(const double* W, int64_t n_pad, int ncols, double* F,
+                                   hipStream_t st);
+hipError_t launch_slab_to_colmajor(const double* W, int64_t n_pad, int64_t n, int64_t col0,
+                                   int64_t ncols, double* out, int64_t ldo, hipStream_t st);
+hipError_t launch_gram(const double* F, int64_t n, int pL, int t, double* STL, double* CT,
+                       hipStream_t st);
+hipError_t launch_assemble_solve(const AsmTable& tab, int64_t ngroups, hipStream_t st);
+
+}  // namespace gls

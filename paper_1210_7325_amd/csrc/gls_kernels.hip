@@ -1,0 +1,727 @@
+// Device kernels of the GLS-sequence solver (gfx950 / CDNA4).
+//
+// Paper: Fabregat-Traver, Aulchenko, Bientinesi, "Solving Sequences of
+// Generalized Least-Squares Problems on Multi-threaded Architectures".
+// The kernels implement the steps of the in-core algorithm "hp-gwas"
+// (Sec. 2, Alg. 5): potrf of M, trsm of X_L / y / the genotype block,
+// syrk/gemv for S_TL and C_T, and per problem the gemv/dot assembly of
+// S_i, c_i (Fig. 1) followed by posv.
+//
+// Layouts (all FP64 unless noted):
+//  * A: the factorization's work matrix, n_pad x n_pad column-major
+//    (n_pad = K*NB), identity on the padded diagonal.
+//  * Packed factor for the triangular solve ("fragment layout"): the strip
+//    of row block k, L[kNB:(k+1)NB, 0:kNB], is stored as a sequence of
+//    k-step pairs; one pair holds, for each 16-row tile, 64 lanes x 2
+//    doubles, lane l of k-step s holding L[row0 + l%16][4s + l/16] (the A
+//    operand of v_mfma_f64_16x16x4f64).  Strip k starts at k(k-1)/2 NB^2.
+//    The inverted diagonal blocks use the same layout with NB columns.
+//  * Whitened genotypes ("slab layout"): columns are grouped in slabs of C;
+//    a slab holds n_pad x C values as k-step pairs of 16-column tiles, lane
+//    l of k-step s holding W[4s + l/16][16ct + l%16] (the B operand).
+//  * FP64 MFMA output: lane l, element i holds D[l/16 + 4i][l%16], which is
+//    exactly the B-operand position of k-step (tile_row0/4 + i) at lane l,
+//    so results go to the slab layout without any lane exchange.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <math.h>
+
+#include "gls_internal.h"
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
+
+#define MFMA64(a, b, c) __builtin_amdgcn_mfma_f64_16x16x4f64((a), (b), (c), 0, 0, 0)
+
+namespace gls {
+
+// ---------------------------------------------------------------------------
+// small helpers
+__device__ __forceinline__ double bcast_lane(double v, int src) {
+  // v of lane `src` to every lane (src is wave-uniform)
+  int2 x = *reinterpret_cast<int2*>(&v);
+  x.x = __builtin_amdgcn_readlane(x.x, src);
+  x.y = __builtin_amdgcn_readlane(x.y, src);
+  return *reinterpret_cast<double*>(&x);
+}
+
+__device__ __forceinline__ size_t strip_offset(int k) {
+  return (size_t)k * (size_t)(k - 1) / 2 * (size_t)(NB * NB);
+}
+
+// ---------------------------------------------------------------------------
+// a0: factorization  M = L L^T  (potrf; Alg. 3-5, first line)
+
+// A := lower(M) padded to n_pad with the identity; strict upper part zero.
+__global__ void k_copy_pad(const double* __restrict__ M, int64_t ldm, int64_t n,
+                           double* __restrict__ A, int64_t n_pad) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t j = blockIdx.y;
+  for (; j < n_pad; j += gridDim.y) {
+    if (i >= n_pad) return;
+    double v;
+    if (i < n && j < n) v = (i >= j) ? M[i + j * ldm] : 0.0;
+    else v = (i == j) ? 1.0 : 0.0;
+    A[i + j * n_pad] = v;
+  }
+}
+
+// Unblocked Cholesky of the diagonal block k in LDS, then its inverse.
+// Writes L_kk into A and into Ldiag[k], inv(L_kk) into Linv[k] (NB x NB
+// column-major, lower).  A non-positive or non-finite pivot of a real row
+// sets *info (order of the failing leading minor) and stops the process:
+// every later kernel sees *info != 0 and returns at once.
+__global__ __launch_bounds__(256) void k_potf2_inv(double* __restrict__ A, int64_t lda,
+                                                    int k, int64_t n,
+                                                    double* __restrict__ Ldiag,
+                                                    double* __restrict__ Linv,
+                                                    int* __restrict__ info) {
+  __shared__ double T[NB][NB + 1];
+  __shared__ int fail;
+  if (*info != 0) return;
+  const int tid = threadIdx.x;
+  const int64_t o = (int64_t)k * NB;
+  for (int idx = tid; idx < NB * NB; idx += 256) {
+    int i = idx % NB, j = idx / NB;
+    T[i][j] = (i >= j) ? A[(o + i) + (o + j) * lda] : 0.0;
+  }
+  if (tid == 0) fail = 0;
+  __syncthreads();
+  for (int j = 0; j < NB; j++) {
+    double d = T[j][j];
+    if (!(d > 0.0) || !(d < INFINITY)) {
+      if (tid == 0) fail = (o + j < n) ? (int)(o + j + 1) : -1;
+      break;
+    }
+    double g = sqrt(d);
+    __syncthreads();
+    for (int i = j + 1 + tid; i < NB; i += 256) T[i][j] /= g;
+    if (tid == 0) T[j][j] = g;
+    __syncthreads();
+    const int m = NB - j - 1;
+    for (int idx = tid; idx < m * m; idx += 256) {
+      int i = j + 1 + idx / m, l = j + 1 + idx % m;
+      if (l <= i) T[i][l] -= T[i][j] * T[l][j];
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  if (fail != 0) {
+    if (tid == 0) *info = fail > 0 ? fail : (int)(o + 1);
+    return;
+  }
+  for (int idx = tid; idx < NB * NB; idx += 256) {
+    int i = idx % NB, j = idx / NB;
+    double v = (i >= j) ? T[i][j] : 0.0;
+    A[(o + i) + (o + j) * lda] = v;
+    Ldiag[(size_t)k * NB * NB + idx] = v;
+  }
+  __syncthreads();
+  // in-place inverse, last column first: column j of inv(L) below the
+  // diagonal is -inv(L)[j+1:, j+1:] L[j+1:, j] / L[j][j]
+  __shared__ double s[NB];
+  for (int j = NB - 1; j >= 0; j--) {
+    double djj = 1.0 / T[j][j];
+    for (int i = j + 1 + tid; i < NB; i += 256) {
+      double acc = 0.0;
+      for (int l = j + 1; l <= i; l++) acc += T[i][l] * T[l][j];
+      s[i] = acc;
+    }
+    __syncthreads();
+    for (int i = j + 1 + tid; i < NB; i += 256) T[i][j] = -djj * s[i];
+    if (tid == 0) T[j][j] = djj;
+    __syncthreads();
+  }
+  for (int idx = tid; idx < NB * NB; idx += 256) {
+    int i = idx % NB, j = idx / NB;
+    Linv[(size_t)k * NB * NB + idx] = (i >= j) ? T[i][j] : 0.0;
+  }
+}
+
+// Tile product on MFMA: a 128 x 128 tile computed by 4 waves (64 x 64 each)
+// from column-major operands: acc = sum_l A[i][l] * Bt[j][l] over KD
+// columns (A and Bt are NB-row panels with leading dimension lda / ldb).
+__device__ __forceinline__ void tile_abt(const double* __restrict__ Ap, int64_t lda,
+                                         const double* __restrict__ Bp, int64_t ldb,
+                                         int kd_end, d4 (&acc)[4][4], int wr, int wc,
+                                         int lane, double sign) {
+  const int r16 = lane % 16, k4 = lane / 16;
+  for (int kk = 0; kk < kd_end; kk++) {
+    double a[4], b[4];
+    const int64_t col = 4 * kk + k4;
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+      a[t] = sign * Ap[(wr * 64 + t * 16 + r16) + col * lda];
+      b[t] = Bp[(wc * 64 + t * 16 + r16) + col * ldb];
+    }
+#pragma unroll
+    for (int rt = 0; rt < 4; rt++)
+#pragma unroll
+      for (int ct = 0; ct < 4; ct++) acc[rt][ct] = MFMA64(a[rt], b[ct], acc[rt][ct]);
+  }
+}
+
+// Panel: A[r, k] := A[r, k] * inv(L_kk)^T for every row block r > k.
+__global__ __launch_bounds__(256) void k_panel(double* __restrict__ A, int64_t lda, int k,
+                                               const double* __restrict__ Linv,
+                                               const int* __restrict__ info) {
+  if (*info != 0) return;
+  const int r = k + 1 + blockIdx.x;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int wr = wave / 2, wc = wave % 2;
+  double* Ap = A + (int64_t)r * NB + (int64_t)k * NB * lda;
+  const double* Li = Linv + (size_t)k * NB * NB;
+  d4 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; a++)
+#pragma unroll
+    for (int b = 0; b < 4; b++) acc[a][b] = (d4){0, 0, 0, 0};
+  // inv(L_kk)[j][l] = 0 for l > j: columns of this wave end at wc*64+63
+  tile_abt(Ap, lda, Li, NB, (wc * 64 + 64) / 4, acc, wr, wc, lane, 1.0);
+  __syncthreads();
+#pragma unroll
+  for (int rt = 0; rt < 4; rt++)
+#pragma unroll
+    for (int ct = 0; ct < 4; ct++)
+#pragma unroll
+      for (int i = 0; i < 4; i++)
+        Ap[(wr * 64 + rt * 16 + lane / 16 + 4 * i) + (int64_t)(wc * 64 + ct * 16 + lane % 16) * lda] =
+            acc[rt][ct][i];
+}
+
+// Trailing update: A[r, s] -= A[r, k] A[s, k]^T for k < s <= r < K.
+__global__ __launch_bounds__(256) void k_syrk(double* __restrict__ A, int64_t lda, int k, int K,
+                                              const int* __restrict__ info) {
+  if (*info != 0) return;
+  const int64_t t = blockIdx.x;
+  int i = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while ((int64_t)(i + 1) * (i + 2) / 2 <= t) i++;
+  while ((int64_t)i * (i + 1) / 2 > t) i--;
+  const int j = (int)(t - (int64_t)i * (i + 1) / 2);
+  const int r = k + 1 + i, s = k + 1 + j;
+  if (r >= K) return;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int wr = wave / 2, wc = wave % 2;
+  double* C = A + (int64_t)r * NB + (int64_t)s * NB * lda;
+  d4 acc[4][4];
+#pragma unroll
+  for (int rt = 0; rt < 4; rt++)
+#pragma unroll
+    for (int ct = 0; ct < 4; ct++)
+#pragma unroll
+      for (int e = 0; e < 4; e++)
+        acc[rt][ct][e] = C[(wr * 64 + rt * 16 + lane / 16 + 4 * e) + (int64_t)(wc * 64 + ct * 16 + lane % 16) * lda];
+  tile_abt(A + (int64_t)r * NB + (int64_t)k * NB * lda, lda,
+           A + (int64_t)s * NB + (int64_t)k * NB * lda, lda, NB / 4, acc, wr, wc, lane, -1.0);
+#pragma unroll
+  for (int rt = 0; rt < 4; rt++)
+#pragma unroll
+    for (int ct = 0; ct < 4; ct++)
+#pragma unroll
+      for (int e = 0; e < 4; e++)
+        C[(wr * 64 + rt * 16 + lane / 16 + 4 * e) + (int64_t)(wc * 64 + ct * 16 + lane % 16) * lda] = acc[rt][ct][e];
+}
+
+// Pack L's off-diagonal strips and the inverted diagonal blocks into the
+// fragment layout.  Block (k, j) of the grid: j < k packs L[k, j] into
+// strip k; j == k packs inv(L_kk).  FP32 copies are written when Lstrips32
+// is not null (FP32_REFINE form).
+__global__ __launch_bounds__(256) void k_pack(const double* __restrict__ A, int64_t lda,
+                                              const double* __restrict__ Linv,
+                                              double* __restrict__ Lstrips,
+                                              double* __restrict__ LinvP,
+                                              float* __restrict__ Lstrips32, int K) {
+  const int64_t t = blockIdx.x;  // enumerates (k, j), 0 <= j <= k < K
+  int k = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while ((int64_t)(k + 1) * (k + 2) / 2 <= t) k++;
+  while ((int64_t)k * (k + 1) / 2 > t) k--;
+  const int j = (int)(t - (int64_t)k * (k + 1) / 2);
+  for (int d = threadIdx.x; d < NB * NB; d += 256) {
+    // d = ((kp * (NB/16) + rt) * 64 + lane) * 2 + kk, with kp local to block j
+    const int kk = d & 1, lane = (d >> 1) & 63, rt = (d >> 7) % (NB / 16), kp = (d >> 7) / (NB / 16);
+    const int row = rt * 16 + lane % 16;       // within the block
+    const int colb = (2 * kp + kk) * 4 + lane / 16;
+    if (j < k) {
+      const double v = A[((int64_t)k * NB + row) + ((int64_t)j * NB + colb) * lda];
+      const size_t dst = strip_offset(k) + (size_t)j * NB * NB + d;
+      Lstrips[dst] = v;
+      if (Lstrips32) Lstrips32[dst] = (float)v;
+    } else {
+      LinvP[(size_t)k * NB * NB + d] = Linv[(size_t)k * NB * NB + row + (size_t)colb * NB];
+    }
+  }
+}
+
+// Unpack the factor (strips + diagonal blocks) to a caller's column-major
+// n x n array; the strict upper triangle is zeroed.
+__global__ void k_unpack_factor(const double* __restrict__ Lstrips,
+                                const double* __restrict__ Ldiag, int64_t n,
+                                double* __restrict__ L, int64_t ldl) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t j = blockIdx.y; j < n; j += gridDim.y) {
+    if (i >= n) return;
+    double v = 0.0;
+    if (i >= j) {
+      const int kb = (int)(i / NB), jb = (int)(j / NB);
+      const int row = (int)(i % NB), colb = (int)(j % NB);
+      if (kb == jb) {
+        v = Ldiag[(size_t)kb * NB * NB + row + (size_t)colb * NB];
+      } else {
+        const int col = (int)j;
+        const int ks = col / 4, kp_ = ks / 2, kk = ks % 2;
+        const int lane = (col % 4) * 16 + row % 16, rt = row / 16;
+        v = Lstrips[strip_offset(kb) + ((size_t)kp_ * (NB / 16) + rt) * 128 + lane * 2 + kk];
+      }
+    }
+    L[i + j * ldl] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a1/a2: blocked lower triangular solve  W = L^{-1} X  (the trsm of Alg. 5,
+// grouped over many right-hand sides as the paper prescribes)
+//
+// One work-group owns a slab of C columns and walks the row blocks
+// k = 0..K-1 (left-looking):
+//   R_k = X_k - sum_{j<k} L_kj W_j     FP64 MFMA, operands streamed from the
+//                                      packed strip and the slab's own W
+//   W_k = inv(L_kk) R_k                FP64 MFMA, R_k staged in LDS
+// The waves split the NB rows of a block (WR ways) and the C columns (WC
+// ways).  X is int8 genotypes (exact in FP64) or FP64 (fixed part).
+template <typename TIn>
+__device__ __forceinline__ double load_x(const TIn* __restrict__ X, int64_t ldx, int64_t row,
+                                         int64_t col, int64_t n, int64_t ncols) {
+  return (row < n && col < ncols) ? (double)X[col * ldx + row] : 0.0;
+}
+
+template <int C, int WR, int WC, typename TIn>
+__global__ __launch_bounds__(64 * WR * WC) void k_trsm(const JobTable tab) {
+  constexpr int RW = NB / WR, RT = RW / 16;
+  constexpr int CW = C / WC, CT = CW / 16;
+  constexpr int CTS = C / 16;  // column tiles per slab
+  static_assert(RT >= 1 && CT >= 1, "tile shape");
+  __shared__ __attribute__((aligned(16))) double Rl[NB * C];
+
+  // find the job of this slab
+  int jb = 0;
+  while (jb + 1 < tab.njobs && (int64_t)blockIdx.x >= tab.j[jb + 1].slab0) jb++;
+  const JobDesc& J = tab.j[jb];
+  const int64_t slab = (int64_t)blockIdx.x - J.slab0;
+  const int K = J.K;
+  const int64_t n = J.n, ncols = J.ncols;
+  const TIn* __restrict__ X = reinterpret_cast<const TIn*>(J.X);
+  const int64_t ldx = J.ldx;
+  const double* __restrict__ Lstrips = J.Lstrips;
+  const double* __restrict__ LinvP = J.LinvP;
+  double* __restrict__ Wslab = J.W + slab * (int64_t)K * NB * C;
+
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int wr = wave / WC, wc = wave % WC;
+  const int64_t col_base = slab * C + wc * CW;
+
+  for (int k = 0; k < K; k++) {
+    d4 acc[RT][CT];
+#pragma unroll
+    for (int a = 0; a < RT; a++)
+#pragma unroll
+      for (int b = 0; b < CT; b++) acc[a][b] = (d4){0, 0, 0, 0};
+
+    // R_k accumulation over the previous row blocks
+    const double* __restrict__ Ls = Lstrips + strip_offset(k) + (size_t)(wr * RT) * 128 + lane * 2;
+    const double* __restrict__ Wb = Wslab + (size_t)(wc * CT) * 128 + lane * 2;
+    const int npairs = k * (NB / 8);
+    for (int kp = 0; kp < npairs; kp++) {
+      d2 a[RT], b[CT];
+#pragma unroll
+      for (int rt = 0; rt < RT; rt++)
+        a[rt] = *reinterpret_cast<const d2*>(Ls + ((size_t)kp * (NB / 16) + rt) * 128);
+#pragma unroll
+      for (int ct = 0; ct < CT; ct++)
+        b[ct] = *reinterpret_cast<const d2*>(Wb + ((size_t)kp * CTS + ct) * 128);
+#pragma unroll
+      for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+        for (int ct = 0; ct < CT; ct++) {
+          acc[rt][ct] = MFMA64(a[rt].x, b[ct].x, acc[rt][ct]);
+          acc[rt][ct] = MFMA64(a[rt].y, b[ct].y, acc[rt][ct]);
+        }
+    }
+
+    // R_k = X_k - acc, staged in LDS in the B-operand pair layout
+#pragma unroll
+    for (int rt = 0; rt < RT; rt++) {
+      const int rowl = wr * RW + rt * 16;  // row of the tile within the block
+#pragma unroll
+      for (int ct = 0; ct < CT; ct++) {
+        const int64_t col = col_base + ct * 16 + lane % 16;
+        double r[4];
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+          const int64_t row = (int64_t)k * NB + rowl + lane / 16 + 4 * i;
+          r[i] = load_x<TIn>(X, ldx, row, col, n, ncols) - acc[rt][ct][i];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; i += 2) {
+          const int kp = (rowl / 4 + i) / 2;
+          *reinterpret_cast<d2*>(&Rl[((size_t)kp * CTS + wc * CT + ct) * 128 + lane * 2]) =
+              (d2){r[i], r[i + 1]};
+        }
+      }
+    }
+    __syncthreads();
+
+    // W_k = inv(L_kk) R_k ; inv(L_kk) is lower triangular, so the k-steps
+    // beyond this wave's last row are zero and skipped
+#pragma unroll
+    for (int a = 0; a < RT; a++)
+#pragma unroll
+      for (int b = 0; b < CT; b++) acc[a][b] = (d4){0, 0, 0, 0};
+    const double* __restrict__ Li = LinvP + (size_t)k * NB * NB + (size_t)(wr * RT) * 128 + lane * 2;
+    const int kp_end = (wr * RW + RW) / 8;
+    for (int kp = 0; kp < kp_end; kp++) {
+      d2 a[RT], b[CT];
+#pragma unroll
+      for (int rt = 0; rt < RT; rt++)
+        a[rt] = *reinterpret_cast<const d2*>(Li + ((size_t)kp * (NB / 16) + rt) * 128);
+#pragma unroll
+      for (int ct = 0; ct < CT; ct++)
+        b[ct] = *reinterpret_cast<const d2*>(&Rl[((size_t)kp * CTS + wc * CT + ct) * 128 + lane * 2]);
+#pragma unroll
+      for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+        for (int ct = 0; ct < CT; ct++) {
+          acc[rt][ct] = MFMA64(a[rt].x, b[ct].x, acc[rt][ct]);
+          acc[rt][ct] = MFMA64(a[rt].y, b[ct].y, acc[rt][ct]);
+        }
+    }
+    // store W_k (slab layout): element i of the FP64 output is k-step
+    // (row0/4 + i) at the same lane
+#pragma unroll
+    for (int rt = 0; rt < RT; rt++) {
+      const int64_t ks0 = (int64_t)k * (NB / 4) + (wr * RW + rt * 16) / 4;
+#pragma unroll
+      for (int ct = 0; ct < CT; ct++)
+#pragma unroll
+        for (int i = 0; i < 4; i += 2)
+          *reinterpret_cast<d2*>(Wslab + ((size_t)((ks0 + i) / 2) * CTS + wc * CT + ct) * 128 + lane * 2) =
+              (d2){acc[rt][ct][i], acc[rt][ct][i + 1]};
+    }
+    __threadfence_block();
+    __syncthreads();
+  }
+}
+
+// Address of W(row, col) in the slab layout.
+__device__ __forceinline__ size_t slab_index(int64_t row, int64_t col, int C, int64_t n_pad) {
+  const int64_t slab = col / C, cc = col % C;
+  const int64_t ks = row / 4;
+  return (size_t)slab * n_pad * C + ((size_t)(ks / 2) * (C / 16) + cc / 16) * 128 +
+         (size_t)(((row % 4) * 16 + cc % 16) * 2 + (ks % 2));
+}
+
+// Slab layout -> row-major n_pad x ld (the fixed part F = [W_L | ytil]).
+__global__ void k_slab_to_rowmajor(const double* __restrict__ W, int C, int64_t n_pad,
+                                   int ncols, double* __restrict__ F) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n_pad * ncols) return;
+  int64_t r = idx / ncols;
+  int c = (int)(idx % ncols);
+  F[idx] = W[slab_index(r, c, C, n_pad)];
+}
+
+// Slab layout -> caller's column-major array (inspection).
+__global__ void k_slab_to_colmajor(const double* __restrict__ W, int C, int64_t n_pad, int64_t n,
+                                   int64_t col0, int64_t ncols, double* __restrict__ out, int64_t ldo) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t c = blockIdx.y; c < ncols; c += gridDim.y) {
+    if (r >= n) return;
+    out[r + c * ldo] = W[slab_index(r, col0 + c, C, n_pad)];
+  }
+}
+
+// Pack [X_L | Y] (two column-major inputs) into one n x (pL+t) buffer.
+__global__ void k_pack_fixed(const double* __restrict__ XL, int64_t ldx, const double* __restrict__ Y,
+                             int64_t ldy, int64_t n, int pL, int t, double* __restrict__ out) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int c = blockIdx.y;
+  if (r >= n) return;
+  out[r + c * n] = (c < pL) ? XL[r + c * ldx] : Y[r + (c - pL) * ldy];
+}
+
+// S_TL = W_L^T W_L and C_T = W_L^T ytil (syrk / gemv of Alg. 5): one
+// work-group per entry (a, b) of G = F^T F, fixed-order reduction.
+__global__ __launch_bounds__(256) void k_gram(const double* __restrict__ F, int64_t n, int ld,
+                                              int pL, int t, double* __restrict__ STL,
+                                              double* __restrict__ CT) {
+  const int a = blockIdx.x, b = blockIdx.y;  // a < pL, b < pL + t
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int64_t r = threadIdx.x; r < n; r += 256) s += F[r * ld + a] * F[r * ld + b];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (b < pL) STL[a + b * pL] = red[0];
+    else CT[a + (b - pL) * pL] = red[0];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a3/a4: per-problem assembly and solve (Alg. 5 loop body: S_BL_i, S_BR_i,
+// b_B_i by gemv/dot, then posv of the p x p system; Fig. 1 partition).
+//
+// One work-group per group of G = 16 / p_R problems (G p_R <= 16 columns).
+// Lane (rg, cl) of wave w reads W(4s + rg, col0 + cl) for s = w, w+NW, ...
+// (512 contiguous bytes per wave and step in the slab layout) and keeps
+// dot products with the rows of F = [W_L | ytil] and with the other
+// columns of its problem.  After a fixed-order reduction the p x p system
+// S_i = [S_TL, S_BL_i^T; S_BL_i, S_BR_i] and c_i = [C_T; C_B_i] are built in
+// LDS and each problem is solved by one wavefront: Cholesky, forward and
+// backward substitution with lane j holding column j of S_i and row j of
+// c_i, and wave-wide broadcasts (v_readlane) between the steps.
+constexpr int AS_WAVES = 8;
+
+__global__ __launch_bounds__(64 * AS_WAVES) void k_assemble_solve(const AsmTable tab) {
+  __shared__ double red[AS_WAVES][16][MAXP + MAXT + 16];
+  __shared__ double Ssh[16][MAXP * MAXP];
+  __shared__ double Csh[16][MAXP * MAXT];
+
+  int jb = 0;
+  while (jb + 1 < tab.njobs && (int64_t)blockIdx.x >= tab.j[jb + 1].grp0) jb++;
+  const AsmDesc& J = tab.j[jb];
+  const int pL = J.pL, pR = J.pR, t = J.t, p = pL + pR;
+  const int G = 16 / pR;
+  const int64_t grp = (int64_t)blockIdx.x - J.grp0;
+  const int64_t snp0 = grp * G;
+  const int ng = (int)((J.nsnp - snp0) < G ? (J.nsnp - snp0) : G);
+  const int nc = ng * pR;
+  const int64_t col0 = snp0 * pR;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int rg = lane / 16, cl = lane % 16;
+  const bool valid = cl < nc;
+  const int q = valid ? cl % pR : 0;
+  const int first = rg * 16 + (valid ? cl - q : 0);
+  const int ldf = pL + t;
+  const int nR = pL + t + pR;
+
+  double acc[MAXP + MAXT + 16];
+#pragma unroll
+  for (int e = 0; e < MAXP + MAXT + 16; e++) acc[e] = 0.0;
+
+  const int64_t nsteps = (J.n + 3) / 4;
+  const int64_t mycol = col0 + (valid ? cl : 0);
+  for (int64_t s = wave; s < nsteps; s += AS_WAVES) {
+    const int64_t row = 4 * s + rg;
+    const double w = valid ? J.W[slab_index(row, mycol, J.C, J.n_pad)] : 0.0;
+    const double* __restrict__ f = J.F + row * ldf;
+#pragma unroll
+    for (int e = 0; e < MAXP + MAXT; e++)
+      if (e < ldf) acc[e] += w * f[e];
+#pragma unroll
+    for (int e = 0; e < 16; e++)
+      if (e < pR) {
+        int src = first + e;
+        src = src < rg * 16 + 15 ? src : rg * 16 + 15;
+        acc[MAXP + MAXT + e] += w * __shfl(w, src);
+      }
+  }
+  // reduce over the 4 row phases of the wave, then over waves (fixed order)
+#pragma unroll
+  for (int e = 0; e < MAXP + MAXT + 16; e++) {
+    double v = acc[e];
+    v += __shfl_xor(v, 16);
+    v += __shfl_xor(v, 32);
+    acc[e] = v;
+  }
+  if (rg == 0) {
+#pragma unroll
+    for (int e = 0; e < MAXP + MAXT; e++)
+      if (e < ldf) red[wave][cl][e] = acc[e];
+#pragma unroll
+    for (int e = 0; e < 16; e++)
+      if (e < pR) red[wave][cl][ldf + e] = acc[MAXP + MAXT + e];
+  }
+  __syncthreads();
+  // assemble S_i and c_i for the ng problems
+  for (int idx = threadIdx.x; idx < ng * p * p; idx += 64 * AS_WAVES) {
+    const int g = idx / (p * p), a = (idx % (p * p)) % p, b = (idx % (p * p)) / p;
+    double v;
+    if (a < pL && b < pL) {
+      v = J.STL[a + b * pL];
+    } else if (a >= pL && b >= pL) {
+      const int c = g * pR + (a - pL);
+      v = 0.0;
+      for (int w = 0; w < AS_WAVES; w++) v += red[w][c][ldf + (b - pL)];
+    } else {
+      const int qa = a >= pL ? a - pL : b - pL;   // genotype column of the problem
+      const int l = a >= pL ? b : a;              // fixed column
+      const int c = g * pR + qa;
+      v = 0.0;
+      for (int w = 0; w < AS_WAVES; w++) v += red[w][c][l];
+    }
+    Ssh[g][a + b * p] = v;
+  }
+  for (int idx = threadIdx.x; idx < ng * p * t; idx += 64 * AS_WAVES) {
+    const int g = idx / (p * t), a = (idx % (p * t)) % p, j = (idx % (p * t)) / p;
+    double v;
+    if (a < pL) {
+      v = J.CT[a + j * pL];
+    } else {
+      const int c = g * pR + (a - pL);
+      v = 0.0;
+      for (int w = 0; w < AS_WAVES; w++) v += red[w][c][pL + j];
+    }
+    Csh[g][a + j * p] = v;
+  }
+  __syncthreads();
+
+  // one wavefront per problem
+  for (int g = wave; g < ng; g += AS_WAVES) {
+    double col[MAXP], crow[MAXT];
+#pragma unroll
+    for (int a = 0; a < MAXP; a++) col[a] = (lane < p && a < p) ? Ssh[g][a + lane * p] : 0.0;
+#pragma unroll
+    for (int j = 0; j < MAXT; j++) crow[j] = (lane < p && j < t) ? Csh[g][lane + j * p] : 0.0;
+    int fail = 0;
+    for (int k = 0; k < p; k++) {
+      double d = 0.0;
+#pragma unroll
+      for (int a = 0; a < MAXP; a++)
+        if (a == k) d = bcast_lane(col[a], k);
+      if (!(d > 0.0) || !(d < INFINITY)) { fail = k + 1; break; }
+      const double gdiag = sqrt(d);
+      if (lane == k) {
+#pragma unroll
+        for (int a = 0; a < MAXP; a++) {
+          if (a > k) col[a] = col[a] / gdiag;
+          else if (a == k) col[a] = gdiag;
+        }
+      }
+      double gk[MAXP];
+      double gmine = 0.0;
+#pragma unroll
+      for (int a = 0; a < MAXP; a++) {
+        gk[a] = (a > k && a < p) ? bcast_lane(col[a], k) : 0.0;
+        if (a == lane) gmine = gk[a];
+      }
+      if (lane > k && lane < p) {
+#pragma unroll
+        for (int a = 0; a < MAXP; a++)
+          if (a >= lane) col[a] -= gk[a] * gmine;
+      }
+      // forward substitution step with the new column of the factor
+#pragma unroll
+      for (int j = 0; j < MAXT; j++) {
+        if (j < t) {
+          const double zk = bcast_lane(crow[j], k) / gdiag;
+          if (lane == k) crow[j] = zk;
+          else if (lane > k && lane < p) crow[j] -= gmine * zk;
+        }
+      }
+    }
+    if (!fail) {
+      for (int k = p - 1; k >= 0; k--) {
+        double gkk = 0.0, gki = 0.0;
+#pragma unroll
+        for (int a = 0; a < MAXP; a++)
+          if (a == k) { gkk = bcast_lane(col[a], k); gki = col[a]; }
+#pragma unroll
+        for (int j = 0; j < MAXT; j++) {
+          if (j < t) {
+            const double bk = bcast_lane(crow[j], k) / gkk;
+            if (lane == k) crow[j] = bk;
+            else if (lane < k) crow[j] -= gki * bk;
+          }
+        }
+      }
+    }
+    const int64_t i = snp0 + g;
+    if (lane < p) {
+#pragma unroll
+      for (int j = 0; j < MAXT; j++)
+        if (j < t) J.B[(i * t + j) * J.ldb + lane] = fail ? NAN : crow[j];
+    }
+    if (lane == 0 && J.info) J.info[i] = fail;
+  }
+}
+
+}  // namespace gls
+
+// ---------------------------------------------------------------------------
+// launchers (host side, used by gls_api.cpp)
+namespace gls {
+
+hipError_t launch_factor(const double* M, int64_t ldm, int64_t n, int64_t n_pad, int K,
+                         double* A, double* Ldiag, double* Linv, double* Lstrips, double* LinvP,
+                         float* Lstrips32, int* dinfo, hipStream_t st) {
+  {
+    dim3 grid((unsigned)((n_pad + 255) / 256), (unsigned)(n_pad < 65535 ? n_pad : 65535));
+    k_copy_pad<<<grid, 256, 0, st>>>(M, ldm, n, A, n_pad);
+  }
+  for (int k = 0; k < K; k++) {
+    k_potf2_inv<<<1, 256, 0, st>>>(A, n_pad, k, n, Ldiag, Linv, dinfo);
+    if (k + 1 < K) {
+      k_panel<<<K - 1 - k, 256, 0, st>>>(A, n_pad, k, Linv, dinfo);
+      const int64_t d = K - 1 - k;
+      k_syrk<<<(unsigned)(d * (d + 1) / 2), 256, 0, st>>>(A, n_pad, k, K, dinfo);
+    }
+  }
+  const int64_t nblk = (int64_t)K * (K + 1) / 2;
+  k_pack<<<(unsigned)nblk, 256, 0, st>>>(A, n_pad, Linv, Lstrips, LinvP, Lstrips32, K);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack_factor(const double* Lstrips, const double* Ldiag, int64_t n, double* L,
+                                int64_t ldl, hipStream_t st) {
+  dim3 grid((unsigned)((n + 255) / 256), (unsigned)(n < 65535 ? n : 65535));
+  k_unpack_factor<<<grid, 256, 0, st>>>(Lstrips, Ldiag, n, L, ldl);
+  return hipGetLastError();
+}
+
+hipError_t launch_trsm_i8(const JobTable& tab, int64_t nslabs, hipStream_t st) {
+  k_trsm<TRSM_C, TRSM_WR, TRSM_WC, int8_t><<<(unsigned)nslabs, 64 * TRSM_WR * TRSM_WC, 0, st>>>(tab);
+  return hipGetLastError();
+}
+
+hipError_t launch_trsm_f64(const JobTable& tab, int64_t nslabs, hipStream_t st) {
+  k_trsm<TRSM_C, TRSM_WR, TRSM_WC, double><<<(unsigned)nslabs, 64 * TRSM_WR * TRSM_WC, 0, st>>>(tab);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_fixed(const double* XL, int64_t ldx, const double* Y, int64_t ldy, int64_t n,
+                             int pL, int t, double* out, hipStream_t st) {
+  dim3 grid((unsigned)((n + 255) / 256), (unsigned)(pL + t));
+  k_pack_fixed<<<grid, 256, 0, st>>>(XL, ldx, Y, ldy, n, pL, t, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_slab_to_rowmajor(const double* W, int64_t n_pad, int ncols, double* F,
+                                   hipStream_t st) {
+  const int64_t total = n_pad * ncols;
+  k_slab_to_rowmajor<<<(unsigned)((total + 255) / 256), 256, 0, st>>>(W, TRSM_C, n_pad, ncols, F);
+  return hipGetLastError();
+}
+
+hipError_t launch_slab_to_colmajor(const double* W, int64_t n_pad, int64_t n, int64_t col0,
+                                   int64_t ncols, double* out, int64_t ldo, hipStream_t st) {
+  dim3 grid((unsigned)((n + 255) / 256), (unsigned)(ncols < 65535 ? ncols : 65535));
+  k_slab_to_colmajor<<<grid, 256, 0, st>>>(W, TRSM_C, n_pad, n, col0, ncols, out, ldo);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram(const double* F, int64_t n, int pL, int t, double* STL, double* CT,
+                       hipStream_t st) {
+  dim3 grid((unsigned)pL, (unsigned)(pL + t));
+  k_gram<<<grid, 256, 0, st>>>(F, n, pL + t, pL, t, STL, CT);
+  return hipGetLastError();
+}
+
+hipError_t launch_assemble_solve(const AsmTable& tab, int64_t ngroups, hipStream_t st) {
+  k_assemble_solve<<<(unsigned)ngroups, 64 * AS_WAVES, 0, st>>>(tab);
+  return hipGetLastError();
+}
+
+}  // namespace gls

@@ -1,0 +1,299 @@
+"""Python binding of the solver's C ABI (include/gls.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of libgls.so.  PyTorch supplies device memory and streams.  The
+library must have been built (python -m paper_1210_7325_amd.build); loading
+fails loudly otherwise, there is no fallback.
+
+Two levels:
+  * the raw entry points, same names and arguments as the C functions
+    (pointers and streams as Python ints), raising GLSError on failure;
+  * Cohort, a small convenience class over torch tensors.
+
+Matrices are column-major: a (rows, cols) tensor with stride(0) == 1.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libgls.so")
+
+GLS_FP64 = 0
+GLS_FP32_REFINE = 1
+PRECISIONS = {"fp64": GLS_FP64, "fp32_refine": GLS_FP32_REFINE}
+
+GLS_OK, GLS_E_NOT_SPD, GLS_E_STATE, GLS_E_OOM, GLS_E_HIP, GLS_E_UNSUPPORTED = 0, 1, 2, 3, 4, 5
+
+EXPORTS = ("gls_factor", "gls_whiten_fixed", "gls_solve_block", "gls_reserve", "gls_free",
+           "gls_fork", "gls_set_stream", "gls_footprint_bytes", "gls_last_info",
+           "gls_strerror", "gls_copy_factor", "gls_copy_fixed", "gls_whiten_block",
+           "gls_solve_multi")
+
+_i64, _p, _int = ctypes.c_int64, ctypes.c_void_p, ctypes.c_int
+
+
+class gls_work(ctypes.Structure):
+    _fields_ = [("h", _p), ("nsnp", _i64), ("p_R", _i64), ("X_R", _p), ("ldxr", _i64),
+                ("B", _p), ("ldb", _i64), ("info", _p)]
+
+
+class GLSError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where} failed: code {code} ({strerror(code)})")
+
+
+_LIB = None
+
+
+def lib() -> ctypes.CDLL:
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run python -m paper_1210_7325_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        sig = {
+            "gls_factor": (_int, [ctypes.POINTER(_p), _i64, _p, _i64, _int, _p]),
+            "gls_whiten_fixed": (_int, [_p, _i64, _p, _i64, _i64, _p, _i64, _i64]),
+            "gls_solve_block": (_int, [_p, _i64, _i64, _p, _i64, _p, _i64, _p]),
+            "gls_reserve": (_int, [_p, _i64]),
+            "gls_free": (None, [_p]),
+            "gls_fork": (_int, [_p, _p, ctypes.POINTER(_p)]),
+            "gls_set_stream": (_int, [_p, _p]),
+            "gls_footprint_bytes": (ctypes.c_size_t, [_i64, _i64, _i64, _i64, _int]),
+            "gls_last_info": (_int, [_p]),
+            "gls_strerror": (ctypes.c_char_p, [_int]),
+            "gls_copy_factor": (_int, [_p, _p, _i64]),
+            "gls_copy_fixed": (_int, [_p, _p, _i64, _p, _i64, _p, _p]),
+            "gls_whiten_block": (_int, [_p, _i64, _p, _i64, _p, _i64]),
+            "gls_solve_multi": (_int, [ctypes.POINTER(gls_work), _i64, _p]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+def strerror(code: int) -> str:
+    try:
+        return lib().gls_strerror(code).decode()
+    except ImportError:
+        return "?"
+
+
+def _chk(rc: int, where: str) -> int:
+    if rc != 0:
+        raise GLSError(rc, where)
+    return rc
+
+
+# ---- raw entry points (same names as the C ABI) ------------------------------
+def gls_factor(n: int, M: int, ldm: int, prec: int, stream: int) -> Tuple[int, int]:
+    """Returns (return code, handle); GLS_E_NOT_SPD still yields a handle."""
+    h = _p()
+    rc = lib().gls_factor(ctypes.byref(h), n, M, ldm, prec, stream)
+    return rc, (h.value or 0)
+
+
+def gls_whiten_fixed(h, p_L, X_L, ldx, t, Y, ldy, intercept_col) -> int:
+    return lib().gls_whiten_fixed(h, p_L, X_L, ldx, t, Y, ldy, intercept_col)
+
+
+def gls_solve_block(h, nsnp, p_R, X_R, ldxr, B, ldb, info) -> int:
+    return lib().gls_solve_block(h, nsnp, p_R, X_R, ldxr, B, ldb, info)
+
+
+def gls_reserve(h, max_cols) -> int:
+    return lib().gls_reserve(h, max_cols)
+
+
+def gls_free(h) -> None:
+    lib().gls_free(h)
+
+
+def gls_fork(h, stream) -> Tuple[int, int]:
+    out = _p()
+    rc = lib().gls_fork(h, stream, ctypes.byref(out))
+    return rc, (out.value or 0)
+
+
+def gls_set_stream(h, stream) -> int:
+    return lib().gls_set_stream(h, stream)
+
+
+def gls_footprint_bytes(n, p_L, t, max_cols, prec) -> int:
+    return int(lib().gls_footprint_bytes(n, p_L, t, max_cols, prec))
+
+
+def gls_last_info(h) -> int:
+    return lib().gls_last_info(h)
+
+
+def gls_strerror(code) -> str:
+    return strerror(code)
+
+
+def gls_copy_factor(h, L, ldl) -> int:
+    return lib().gls_copy_factor(h, L, ldl)
+
+
+def gls_copy_fixed(h, WL, ldwl, Yt, ldyt, S_TL, C_T) -> int:
+    return lib().gls_copy_fixed(h, WL, ldwl, Yt, ldyt, S_TL, C_T)
+
+
+def gls_whiten_block(h, ncols, X, ldx, W, ldw) -> int:
+    return lib().gls_whiten_block(h, ncols, X, ldx, W, ldw)
+
+
+def gls_solve_multi(items, stream) -> int:
+    arr = (gls_work * len(items))(*items)
+    return lib().gls_solve_multi(arr, len(items), stream)
+
+
+# ---- torch convenience ---------------------------------------------------------
+def _torch():
+    import torch
+    return torch
+
+
+def colmajor(t):
+    """Same values, column-major storage (stride(0) == 1)."""
+    if t.dim() == 1:
+        t = t.reshape(-1, 1)
+    if t.stride(0) == 1 and (t.shape[1] == 1 or t.stride(1) >= t.shape[0]):
+        return t
+    return t.t().contiguous().t()
+
+
+def _ld(t) -> int:
+    return max(int(t.stride(1)) if t.shape[1] > 1 else int(t.shape[0]), 1)
+
+
+def _stream_ptr(stream) -> int:
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+class Cohort:
+    """One cohort: M factored once, fixed part whitened once, then any
+    number of genotype blocks solved (the in-core algorithm, Sec. 2)."""
+
+    def __init__(self, M, precision: str = "fp64", stream=None, _handle: Optional[int] = None):
+        torch = _torch()
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.prec = PRECISIONS[precision]
+        self._keep = []
+        if _handle is not None:
+            self.h = _handle
+            self.n = None
+            return
+        assert M.dtype == torch.float64 and M.is_cuda and M.dim() == 2 and M.shape[0] == M.shape[1]
+        M = colmajor(M)
+        self.n = int(M.shape[0])
+        rc, h = gls_factor(self.n, M.data_ptr(), _ld(M), self.prec, _stream_ptr(self.stream))
+        self.h = h
+        if rc == GLS_E_NOT_SPD:
+            self.info = gls_last_info(h)
+            gls_free(h)
+            self.h = 0
+            raise GLSError(rc, f"gls_factor (leading minor {self.info})")
+        _chk(rc, "gls_factor")
+        self.info = 0
+        self.p_L = self.t = None
+
+    # the fixed part (X_L, y) -------------------------------------------------
+    def whiten_fixed(self, XL, Y, intercept_col: int = 0):
+        torch = _torch()
+        XL = colmajor(XL.to(torch.float64))
+        Y = colmajor(Y.to(torch.float64))
+        self.p_L, self.t = int(XL.shape[1]), int(Y.shape[1])
+        _chk(gls_whiten_fixed(self.h, self.p_L, XL.data_ptr(), _ld(XL), self.t, Y.data_ptr(),
+                              _ld(Y), intercept_col), "gls_whiten_fixed")
+        self._keep = [XL, Y]  # alive until the stream passes the call
+        if self.n is None:
+            self.n = int(XL.shape[0])
+        return self
+
+    def reserve(self, max_cols: int):
+        _chk(gls_reserve(self.h, max_cols), "gls_reserve")
+
+    # blocks of problems -------------------------------------------------------
+    def solve_block(self, XR, p_R: int = 1, B=None, info=None):
+        """XR: int8 (n, nsnp*p_R) column-major on the device.  Returns
+        (B, info) with B of shape (nsnp, t, p) FP64 and info int32 (nsnp,)."""
+        torch = _torch()
+        assert XR.dtype == torch.int8 and XR.is_cuda
+        XR = colmajor(XR)
+        ncols = int(XR.shape[1])
+        assert ncols % p_R == 0
+        nsnp = ncols // p_R
+        p = self.p_L + p_R
+        if B is None:
+            B = torch.empty((nsnp, self.t, p), dtype=torch.float64, device=XR.device)
+        if info is None:
+            info = torch.empty((nsnp,), dtype=torch.int32, device=XR.device)
+        _chk(gls_solve_block(self.h, nsnp, p_R, XR.data_ptr(), _ld(XR), B.data_ptr(), p,
+                             info.data_ptr()), "gls_solve_block")
+        return B, info
+
+    def whiten_block(self, X):
+        torch = _torch()
+        X = colmajor(X)
+        W = torch.empty((X.shape[1], X.shape[0]), dtype=torch.float64, device=X.device).t()
+        _chk(gls_whiten_block(self.h, int(X.shape[1]), X.data_ptr(), _ld(X), W.data_ptr(),
+                              int(X.shape[0])), "gls_whiten_block")
+        return W
+
+    def copy_factor(self):
+        torch = _torch()
+        L = torch.empty((self.n, self.n), dtype=torch.float64, device="cuda").t()
+        _chk(gls_copy_factor(self.h, L.data_ptr(), self.n), "gls_copy_factor")
+        return L
+
+    def copy_fixed(self):
+        torch = _torch()
+        n, pL, t = self.n, self.p_L, self.t
+        WL = torch.empty((pL, n), dtype=torch.float64, device="cuda").t()
+        Yt = torch.empty((t, n), dtype=torch.float64, device="cuda").t()
+        STL = torch.empty((pL, pL), dtype=torch.float64, device="cuda").t()
+        CT = torch.empty((t, pL), dtype=torch.float64, device="cuda").t()
+        _chk(gls_copy_fixed(self.h, WL.data_ptr(), n, Yt.data_ptr(), n, STL.data_ptr(),
+                            CT.data_ptr()), "gls_copy_fixed")
+        return WL, Yt, STL, CT
+
+    def fork(self, stream=None) -> "Cohort":
+        torch = _torch()
+        stream = stream if stream is not None else torch.cuda.Stream()
+        rc, h = gls_fork(self.h, _stream_ptr(stream))
+        _chk(rc, "gls_fork")
+        c = Cohort(None, stream=stream, _handle=h)
+        c.n, c.p_L, c.t, c.prec = self.n, self.p_L, self.t, self.prec
+        return c
+
+    def free(self):
+        if getattr(self, "h", 0):
+            gls_free(self.h)
+            self.h = 0
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def solve_multi(items, stream=None):
+    """items: list of (Cohort, XR, p_R, B, info) solved in one launch per
+    kernel on `stream`."""
+    works = []
+    for c, XR, p_R, B, info in items:
+        works.append(gls_work(c.h, XR.shape[1] // p_R, p_R, XR.data_ptr(), _ld(XR), B.data_ptr(),
+                              c.p_L + p_R, info.data_ptr() if info is not None else None))
+    _chk(gls_solve_multi(works, _stream_ptr(stream)), "gls_solve_multi")

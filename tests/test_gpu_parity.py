@@ -1,0 +1,209 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Tolerance: 1e-10 relative error of b_i (max norm per problem) for the FP64
+path; intermediate quantities (L, W = L^{-1}X, fixed blocks) within 1e-12."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import gls_oracle as orc
+from paper_1210_7325_amd import datagen as dg
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL_B = 1e-10
+TOL_MID = 1e-12
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def G():
+    from paper_1210_7325_amd import gls
+    gls.lib()
+    assert torch.cuda.is_available()
+    return gls
+
+
+def to_dev(a):
+    return torch.from_numpy(np.asfortranarray(a)).cuda()
+
+
+def small_problem(n, pL=3, pR=1, m=40, t=1, seed=0, q=None):
+    w = dg.SMALL.replace(n=n, p_L=pL, p_R=pR, t=t, m=m, q=q or 2 * n, seed=dg.MASTER_SEED + 100 + seed)
+    M = dg.make_M(w)
+    XL = dg.make_XL(w)
+    Y = dg.make_Y(w)
+    XR = dg.make_XR(w, 0, m)
+    return w, M, XL, Y, XR
+
+
+def maxrel(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / np.max(np.abs(np.asarray(b))))
+
+
+@pytest.mark.parametrize("n", [40, 127, 128, 129, 300, 1000])
+def test_factor_matches_cholesky(G, n):
+    say("factor n=", n)
+    w, M, *_ = small_problem(n)
+    c = G.Cohort(to_dev(M))
+    L = c.copy_factor().cpu().numpy()
+    torch.cuda.synchronize()
+    Lref = orc.cholesky_lower(M)
+    assert maxrel(L, Lref) < TOL_MID
+    assert np.all(np.triu(L, 1) == 0)
+    c.free()
+
+
+def test_factor_reports_not_spd(G):
+    say("factor not SPD")
+    n = 300
+    M = np.eye(n)
+    M[200, 200] = -1.0
+    with pytest.raises(G.GLSError) as ei:
+        G.Cohort(to_dev(M))
+    assert ei.value.code == G.GLS_E_NOT_SPD
+    rc, h = G.gls_factor(n, to_dev(M).data_ptr(), n, 0, torch.cuda.current_stream().cuda_stream)
+    assert rc == G.GLS_E_NOT_SPD and G.gls_last_info(h) == 201
+    G.gls_free(h)
+
+
+@pytest.mark.parametrize("n,ncols", [(1000, 200), (129, 65), (300, 1), (513, 130)])
+def test_whiten_block_matches_oracle(G, n, ncols):
+    say("whiten n=", n, "ncols=", ncols)
+    w, M, XL, Y, XR = small_problem(n, m=ncols)
+    c = G.Cohort(to_dev(M))
+    W = c.whiten_block(to_dev(XR)).cpu().numpy()
+    Wref = orc.whiten(orc.cholesky_lower(M), XR)
+    assert maxrel(W, Wref) < TOL_MID
+    c.free()
+
+
+@pytest.mark.parametrize("pL,t", [(3, 1), (16, 1), (5, 8), (1, 2)])
+def test_fixed_part_matches_oracle(G, pL, t):
+    say("fixed pL=", pL, "t=", t)
+    w, M, XL, Y, XR = small_problem(700, pL=pL, t=t)
+    c = G.Cohort(to_dev(M)).whiten_fixed(to_dev(XL), to_dev(Y))
+    WL, Yt, STL, CT = (x.cpu().numpy() for x in c.copy_fixed())
+    WLr, Ytr, STLr, CTr = orc.fixed_blocks(orc.cholesky_lower(M), XL, Y)
+    assert maxrel(WL, WLr) < TOL_MID and maxrel(Yt, Ytr) < TOL_MID
+    assert maxrel(STL, STLr) < TOL_MID and maxrel(CT, CTr) < TOL_MID
+    c.free()
+
+
+def run_gpu(M, XL, Y, XR, pR, block):
+    from paper_1210_7325_amd import gls
+    c = gls.Cohort(to_dev(M)).whiten_fixed(to_dev(XL), to_dev(Y))
+    dXR = to_dev(XR)
+    nsnp = XR.shape[1] // pR
+    outs, infos = [], []
+    for a in range(0, nsnp, block):
+        b = min(nsnp, a + block)
+        B, info = c.solve_block(dXR[:, a * pR:b * pR], p_R=pR)
+        outs.append(B)
+        infos.append(info)
+    B = torch.cat(outs).cpu().numpy()
+    info = torch.cat(infos).cpu().numpy()
+    c.free()
+    return B, info
+
+
+def test_small_workload_parity(G):
+    """The n=1000, p=4, m=10,000 workload in blocks of 4096 (last one partial)."""
+    w = dg.SMALL
+    say("workload", w.name)
+    M, XL, Y, XR = dg.make_all(w)
+    B, info = run_gpu(M, XL, Y, XR, w.p_R, w.block)
+    ref = orc.gls_sequence(M, XL, XR, Y, w.p_R)
+    assert B.shape == ref.shape
+    assert np.all(info == 0)
+    err = orc.relative_error(B, ref)
+    say("max rel err", err.max())
+    assert err.max() < TOL_B
+
+
+@pytest.mark.parametrize("n,pL,pR,t,m,block", [
+    (63, 3, 1, 1, 37, 16), (64, 2, 2, 1, 20, 7), (65, 4, 3, 2, 33, 33), (129, 16, 4, 1, 50, 17),
+    (200, 5, 1, 8, 70, 64), (300, 1, 1, 1, 5, 5), (1500, 3, 1, 1, 300, 256), (257, 19, 1, 3, 40, 40),
+])
+def test_ragged_shapes_parity(G, n, pL, pR, t, m, block):
+    say("ragged", n, pL, pR, t, m, block)
+    w, M, XL, Y, XR = small_problem(n, pL=pL, pR=pR, m=m, t=t, seed=n + pL)
+    B, info = run_gpu(M, XL, Y, XR, pR, block)
+    ref = orc.gls_sequence(M, XL, XR, Y, pR)
+    assert np.all(info == 0)
+    assert orc.relative_error(B, ref).max() < TOL_B
+
+
+def test_rank_deficient_problem_sets_info(G):
+    say("rank deficient")
+    w, M, XL, Y, XR = small_problem(200, m=10)
+    XR = XR.copy()
+    XR[:, 3] = 0  # X_i has a zero column: S_i singular
+    B, info = run_gpu(M, XL, Y, XR, 1, 10)
+    assert info[3] == 4 and np.all(np.isnan(B[3]))
+    keep = [i for i in range(10) if i != 3]
+    assert np.all(info[keep] == 0)
+    ref = orc.gls_sequence(M, XL, XR[:, keep], Y)
+    assert orc.relative_error(B[keep], ref).max() < TOL_B
+
+
+def test_deterministic_and_block_independent(G):
+    say("determinism")
+    w, M, XL, Y, XR = small_problem(500, m=300)
+    B1, _ = run_gpu(M, XL, Y, XR, 1, 300)
+    B2, _ = run_gpu(M, XL, Y, XR, 1, 300)
+    B3, _ = run_gpu(M, XL, Y, XR, 1, 64)
+    assert np.array_equal(B1, B2)
+    # a problem's result does not depend on the block it is solved in
+    assert np.array_equal(B1, B3)
+
+
+def test_multi_cohort_launch_equals_single(G):
+    say("multi")
+    from paper_1210_7325_amd import gls
+    probs = [small_problem(n, pL=pL, pR=pR, m=m, t=t, seed=i)
+             for i, (n, pL, pR, t, m) in enumerate([(300, 3, 1, 1, 100), (700, 5, 2, 2, 64),
+                                                      (129, 2, 1, 1, 30)])]
+    alone, items, cohorts = [], [], []
+    for (w, M, XL, Y, XR), pR in zip(probs, (1, 2, 1)):
+        c = gls.Cohort(to_dev(M)).whiten_fixed(to_dev(XL), to_dev(Y))
+        dXR = to_dev(XR)
+        B, _ = c.solve_block(dXR, p_R=pR)
+        alone.append(B.cpu().numpy())
+        B2 = torch.empty_like(B)
+        info2 = torch.empty(B.shape[0], dtype=torch.int32, device="cuda")
+        items.append((c, dXR, pR, B2, info2))
+        cohorts.append(c)
+    gls.solve_multi(items)
+    torch.cuda.synchronize()
+    for (c, dXR, pR, B2, info2), a in zip(items, alone):
+        assert np.array_equal(B2.cpu().numpy(), a)
+        assert int(info2.abs().sum()) == 0
+    for c in cohorts:
+        c.free()
+
+
+def test_forked_streams_equal(G):
+    say("fork")
+    from paper_1210_7325_amd import gls
+    w, M, XL, Y, XR = small_problem(600, m=512)
+    c = gls.Cohort(to_dev(M)).whiten_fixed(to_dev(XL), to_dev(Y))
+    dXR = to_dev(XR)
+    Bref, _ = c.solve_block(dXR)
+    torch.cuda.synchronize()
+    forks = [c.fork() for _ in range(3)]
+    outs = []
+    for i, f in enumerate(forks):
+        with torch.cuda.stream(f.stream):
+            outs.append(f.solve_block(dXR[:, 128 * i:128 * (i + 1)])[0])
+    torch.cuda.synchronize()
+    for i, o in enumerate(outs):
+        assert np.array_equal(o.cpu().numpy(), Bref[128 * i:128 * (i + 1)].cpu().numpy())
+    for f in forks:
+        f.free()
+    c.free()
