@@ -153,6 +153,25 @@ int gls_copy_fixed(gls_handle h, double* WL, int64_t ldwl, double* Yt,
 int gls_whiten_block(gls_handle h, int64_t ncols, const int8_t* X, int64_t ldx,
                      double* W, int64_t ldw);
 
+/* ---- tuning and measurement -------------------------------------------- */
+
+/* Columns of genotypes per work-group of the triangular-solve kernel: 16,
+ * 32 or 64 (default 64).  A performance knob only: every column is whitened
+ * by the same sequence of operations whatever its slab, so results are
+ * bitwise independent of it.  Items of one gls_solve_multi call must share
+ * the value. */
+int gls_set_slab_cols(gls_handle h, int cols);
+
+/* Kernel timing.  While enabled, every launch of the triangular-solve
+ * kernel (kind 0) and of the assembly/solve kernel (kind 1) made through h
+ * (for gls_solve_multi: through the first item's handle) is bracketed by a
+ * pair of HIP events on the stream it is launched on.  Enabling or
+ * disabling synchronizes h's stream and clears the record.
+ * gls_kernel_time synchronizes on the recorded events and returns the sum
+ * of the bracketed durations in milliseconds and the number of launches. */
+int gls_set_kernel_timing(gls_handle h, int enable);
+int gls_kernel_time(gls_handle h, int kind, double* ms, int64_t* launches);
+
 /* ---- several cohorts in one launch (serving) ----------------------------
  * One work item per block of problems of one handle.  All items are
  * whitened by one launch of the triangular-solve kernel and assembled and

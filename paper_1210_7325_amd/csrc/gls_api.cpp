@@ -7,6 +7,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "gls.h"
 #include "gls_internal.h"
@@ -37,11 +38,20 @@ struct Cohort {
 
 }  // namespace
 
+struct TimedLaunch {
+  hipEvent_t a = nullptr, b = nullptr;
+  int kind = 0;
+};
+
 struct gls_handle_s {
   Cohort* c = nullptr;
   hipStream_t stream = nullptr;
+  int C = DEFAULT_C;           // columns per work-group of the triangular solve
   double* W = nullptr;         // workspace: whitened genotype columns, slab layout
-  int64_t Wcols = 0;           // capacity in columns (multiple of TRSM_C)
+  int64_t Wcols = 0;           // capacity in columns (multiple of C)
+  bool timing = false;         // bracket kernel launches with events
+  std::vector<TimedLaunch> timed;
+  size_t ntimed = 0;
 };
 
 namespace {
@@ -90,7 +100,7 @@ int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 size_t strips_count(int K) { return (size_t)K * (size_t)(K - 1) / 2 * (size_t)NB * NB; }
 
 int ensure_workspace(gls_handle h, int64_t ncols) {
-  const int64_t need = round_up(std::max<int64_t>(ncols, 1), TRSM_C);
+  const int64_t need = round_up(std::max<int64_t>(ncols, 1), 64);
   if (need <= h->Wcols) return GLS_OK;
   HIPCHK(hipStreamSynchronize(h->stream));
   dfree(h->W);
@@ -129,7 +139,7 @@ AsmDesc make_asm(gls_handle h, int64_t grp0, int64_t nsnp, int64_t pR, double* B
   a.B = B;
   a.ldb = ldb;
   a.info = info;
-  a.C = TRSM_C;
+  a.C = h->C;
   a.pL = (int)h->c->pL;
   a.pR = (int)pR;
   a.t = (int)h->c->t;
@@ -151,6 +161,28 @@ int check_block(gls_handle h, int64_t nsnp, int64_t pR, const int8_t* X_R, int64
   if (ldb < p) return -(base + 5);
   return GLS_OK;
 }
+
+// Brackets one kernel launch with a pair of events when timing is on.
+struct TimedScope {
+  gls_handle h;
+  TimedLaunch* p = nullptr;
+  TimedScope(gls_handle h_, int kind) : h(h_) {
+    if (!h || !h->timing) return;
+    if (h->ntimed == h->timed.size()) {
+      TimedLaunch t;
+      if (hipEventCreate(&t.a) != hipSuccess || hipEventCreate(&t.b) != hipSuccess) return;
+      h->timed.push_back(t);
+    }
+    p = &h->timed[h->ntimed++];
+    p->kind = kind;
+    (void)hipEventRecord(p->a, h->stream);
+  }
+  void end() {
+    if (p) (void)hipEventRecord(p->b, h->stream);
+    p = nullptr;
+  }
+  ~TimedScope() { end(); }
+};
 
 }  // namespace
 
@@ -177,8 +209,9 @@ size_t gls_footprint_bytes(int64_t n, int64_t p_L, int64_t t, int64_t max_cols, 
   b += 2 * (size_t)K * NB * NB * 8;                // inverted + plain diagonal blocks
   b += n_pad * n_pad * 8 + (size_t)K * NB * NB * 8;  // factorization work (transient)
   const size_t w = (size_t)(p_L + t);
-  b += n * w * 8 + n_pad * TRSM_C * 8 + n_pad * w * 8 + (w * w) * 8;  // fixed part
-  b += n_pad * (size_t)round_up(std::max<int64_t>(max_cols, 1), TRSM_C) * 8;  // workspace
+  b += n * w * 8 + n_pad * (size_t)round_up((int64_t)w, FIXED_C) * 8 + n_pad * w * 8 +
+       (w * w) * 8;  // fixed part
+  b += n_pad * (size_t)round_up(std::max<int64_t>(max_cols, 1), 64) * 8;  // workspace
   if (prec == GLS_FP32_REFINE) b += strips_count(K) * 4;
   return b;
 }
@@ -273,7 +306,8 @@ int gls_whiten_fixed(gls_handle h, int64_t p_L, const double* X_L, int64_t ldx, 
   const int64_t w = p_L + t;
   int rc;
   if ((rc = dalloc(&c->Xfix, (size_t)c->n * w))) return rc;
-  if ((rc = dalloc(&c->Wfix, (size_t)c->n_pad * TRSM_C))) return rc;
+  const int64_t fix_slabs = (w + FIXED_C - 1) / FIXED_C;
+  if ((rc = dalloc(&c->Wfix, (size_t)c->n_pad * FIXED_C * fix_slabs))) return rc;
   if ((rc = dalloc(&c->F, (size_t)c->n_pad * w))) return rc;
   if ((rc = dalloc(&c->STL, (size_t)p_L * p_L))) return rc;
   if ((rc = dalloc(&c->CT, (size_t)p_L * t))) return rc;
@@ -293,7 +327,7 @@ int gls_whiten_fixed(gls_handle h, int64_t p_L, const double* X_L, int64_t ldx, 
   tab.j[0].LinvP = c->LinvP;
   tab.j[0].W = c->Wfix;
   tab.j[0].K = c->K;
-  HIPCHK(launch_trsm_f64(tab, 1, h->stream));
+  HIPCHK(launch_trsm_f64(tab, fix_slabs, h->stream));
   HIPCHK(launch_slab_to_rowmajor(c->Wfix, c->n_pad, (int)w, c->F, h->stream));
   HIPCHK(launch_gram(c->F, c->n, (int)p_L, (int)t, c->STL, c->CT, h->stream));
   c->fixed = true;
@@ -316,12 +350,16 @@ int gls_solve_block(gls_handle h, int64_t nsnp, int64_t p_R, const int8_t* X_R, 
   JobTable tab;
   tab.njobs = 1;
   tab.j[0] = make_job(h, 0, ncols, X_R, ldxr);
-  HIPCHK(launch_trsm_i8(tab, (ncols + TRSM_C - 1) / TRSM_C, h->stream));
+  TimedScope t0(h, 0);
+  HIPCHK(launch_trsm_i8(tab, (ncols + h->C - 1) / h->C, h->C, h->stream));
+  t0.end();
   AsmTable at;
   at.njobs = 1;
   at.j[0] = make_asm(h, 0, nsnp, p_R, B, ldb, info);
   const int64_t G = 16 / p_R;
+  TimedScope t1(h, 1);
   HIPCHK(launch_assemble_solve(at, (nsnp + G - 1) / G, h->stream));
+  t1.end();
   return GLS_OK;
 }
 
@@ -330,8 +368,10 @@ int gls_solve_multi(const gls_work* items, int64_t count, void* stream) {
   if (count == 0) return GLS_OK;
   if (!items) return -1;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const int C = items[0].h ? items[0].h->C : DEFAULT_C;
   for (int64_t i = 0; i < count; i++) {
     const gls_work& w = items[i];
+    if (w.h && w.h->C != C) return GLS_E_UNSUPPORTED;  // one slab width per launch
     int rc = check_block(w.h, w.nsnp, w.p_R, w.X_R, w.ldxr, w.B, w.ldb, 2);
     if (rc) return rc < 0 ? -1 : rc;
     for (int64_t j = 0; j < i; j++)
@@ -352,13 +392,22 @@ int gls_solve_multi(const gls_work* items, int64_t count, void* stream) {
       if (w.nsnp == 0) continue;
       const int64_t ncols = w.nsnp * w.p_R;
       tab.j[tab.njobs++] = make_job(w.h, slabs, ncols, w.X_R, w.ldxr);
-      slabs += (ncols + TRSM_C - 1) / TRSM_C;
+      slabs += (ncols + C - 1) / C;
       at.j[at.njobs++] = make_asm(w.h, groups, w.nsnp, w.p_R, w.B, w.ldb, w.info);
       groups += (w.nsnp + 16 / w.p_R - 1) / (16 / w.p_R);
     }
     if (tab.njobs == 0) continue;
-    HIPCHK(launch_trsm_i8(tab, slabs, st));
-    HIPCHK(launch_assemble_solve(at, groups, st));
+    gls_handle h0 = items[a].h;
+    hipStream_t keep = h0->stream;
+    h0->stream = st;  // timing events go to the launch stream
+    TimedScope t0(h0, 0);
+    hipError_t e = launch_trsm_i8(tab, slabs, C, st);
+    t0.end();
+    TimedScope t1(h0, 1);
+    if (e == hipSuccess) e = launch_assemble_solve(at, groups, st);
+    t1.end();
+    h0->stream = keep;
+    HIPCHK(e);
   }
   return GLS_OK;
 }
@@ -374,6 +423,7 @@ int gls_fork(gls_handle h, void* stream, gls_handle* out) {
   g->c = h->c;
   g->c->refs.fetch_add(1);
   g->stream = reinterpret_cast<hipStream_t>(stream);
+  g->C = h->C;
   *out = g;
   return GLS_OK;
 }
@@ -382,6 +432,10 @@ void gls_free(gls_handle h) {
   if (!h) return;
   (void)hipStreamSynchronize(h->stream);
   dfree(h->W);
+  for (auto& p : h->timed) {
+    if (p.a) (void)hipEventDestroy(p.a);
+    if (p.b) (void)hipEventDestroy(p.b);
+  }
   if (h->c->refs.fetch_sub(1) == 1) cohort_free(h->c);
   delete h;
 }
@@ -402,8 +456,8 @@ int gls_copy_fixed(gls_handle h, double* WL, int64_t ldwl, double* Yt, int64_t l
   if (WL && ldwl < c->n) return -3;
   if (Yt && ldyt < c->n) return -5;
   if (!c->fixed) return GLS_E_STATE;
-  if (WL) HIPCHK(launch_slab_to_colmajor(c->Wfix, c->n_pad, c->n, 0, c->pL, WL, ldwl, h->stream));
-  if (Yt) HIPCHK(launch_slab_to_colmajor(c->Wfix, c->n_pad, c->n, c->pL, c->t, Yt, ldyt, h->stream));
+  if (WL) HIPCHK(launch_slab_to_colmajor(c->Wfix, FIXED_C, c->n_pad, c->n, 0, c->pL, WL, ldwl, h->stream));
+  if (Yt) HIPCHK(launch_slab_to_colmajor(c->Wfix, FIXED_C, c->n_pad, c->n, c->pL, c->t, Yt, ldyt, h->stream));
   if (S_TL)
     HIPCHK(hipMemcpyAsync(S_TL, c->STL, sizeof(double) * c->pL * c->pL, hipMemcpyDeviceToDevice,
                           h->stream));
@@ -428,8 +482,46 @@ int gls_whiten_block(gls_handle h, int64_t ncols, const int8_t* X, int64_t ldx, 
   JobTable tab;
   tab.njobs = 1;
   tab.j[0] = make_job(h, 0, ncols, X, ldx);
-  HIPCHK(launch_trsm_i8(tab, (ncols + TRSM_C - 1) / TRSM_C, h->stream));
-  HIPCHK(launch_slab_to_colmajor(h->W, h->c->n_pad, h->c->n, 0, ncols, W, ldw, h->stream));
+  TimedScope t0(h, 0);
+  HIPCHK(launch_trsm_i8(tab, (ncols + h->C - 1) / h->C, h->C, h->stream));
+  t0.end();
+  HIPCHK(launch_slab_to_colmajor(h->W, h->C, h->c->n_pad, h->c->n, 0, ncols, W, ldw, h->stream));
+  return GLS_OK;
+}
+
+int gls_set_slab_cols(gls_handle h, int cols) {
+  if (!h) return -1;
+  if (cols != 16 && cols != 32 && cols != 64) return -2;
+  h->C = cols;
+  return GLS_OK;
+}
+
+int gls_set_kernel_timing(gls_handle h, int enable) {
+  if (!h) return -1;
+  HIPCHK(hipStreamSynchronize(h->stream));
+  h->ntimed = 0;
+  h->timing = enable != 0;
+  return GLS_OK;
+}
+
+int gls_kernel_time(gls_handle h, int kind, double* ms, int64_t* launches) {
+  if (!h) return -1;
+  if (kind != 0 && kind != 1) return -2;
+  if (!ms) return -3;
+  if (!launches) return -4;
+  double sum = 0.0;
+  int64_t cnt = 0;
+  for (size_t i = 0; i < h->ntimed; i++) {
+    const TimedLaunch& p = h->timed[i];
+    if (p.kind != kind) continue;
+    HIPCHK(hipEventSynchronize(p.b));
+    float f = 0.f;
+    HIPCHK(hipEventElapsedTime(&f, p.a, p.b));
+    sum += f;
+    cnt++;
+  }
+  *ms = sum;
+  *launches = cnt;
   return GLS_OK;
 }
 

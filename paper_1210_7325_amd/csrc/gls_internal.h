@@ -6,12 +6,15 @@
 namespace gls {
 
 constexpr int NB = 128;       // row block of the factorization and the solve
-constexpr int TRSM_C = 64;    // columns per slab (one work-group)
-constexpr int TRSM_WR = 4;    // waves along the rows of a block
-constexpr int TRSM_WC = 1;    // waves along the columns of a slab
+constexpr int FIXED_C = 16;   // slab width used for the fixed part [X_L | Y]
+constexpr int DEFAULT_C = 64; // default slab width for genotype blocks (16, 32 or 64)
 constexpr int MAXP = 20;      // p = p_L + p_R <= 20 (Sec. 1)
 constexpr int MAXT = 8;       // phenotypes per call
 constexpr int MAX_INLINE_JOBS = 16;
+#ifndef GLS_TRSM_DEPTH
+#define GLS_TRSM_DEPTH 4
+#endif
+constexpr int TRSM_DEPTH = GLS_TRSM_DEPTH;  // k-step pairs in flight in the solve's GEMM loop
 
 // One block of columns of one cohort for the triangular-solve kernel.
 struct JobDesc {
@@ -54,13 +57,13 @@ hipError_t launch_factor(const double* M, int64_t ldm, int64_t n, int64_t n_pad,
                          float* Lstrips32, int* dinfo, hipStream_t st);
 hipError_t launch_unpack_factor(const double* Lstrips, const double* Ldiag, int64_t n, double* L,
                                 int64_t ldl, hipStream_t st);
-hipError_t launch_trsm_i8(const JobTable& tab, int64_t nslabs, hipStream_t st);
+hipError_t launch_trsm_i8(const JobTable& tab, int64_t nslabs, int C, hipStream_t st);
 hipError_t launch_trsm_f64(const JobTable& tab, int64_t nslabs, hipStream_t st);
 hipError_t launch_pack_fixed(const double* XL, int64_t ldx, const double* Y, int64_t ldy, int64_t n,
                              int pL, int t, double* out, hipStream_t st);
 hipError_t launch_slab_to_rowmajor(const double* W, int64_t n_pad, int ncols, double* F,
                                    hipStream_t st);
-hipError_t launch_slab_to_colmajor(const double* W, int64_t n_pad, int64_t n, int64_t col0,
+hipError_t launch_slab_to_colmajor(const double* W, int C, int64_t n_pad, int64_t n, int64_t col0,
                                    int64_t ncols, double* out, int64_t ldo, hipStream_t st);
 hipError_t launch_gram(const double* F, int64_t n, int pL, int t, double* STL, double* CT,
                        hipStream_t st);

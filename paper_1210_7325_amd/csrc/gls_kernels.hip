@@ -294,12 +294,14 @@ __device__ __forceinline__ double load_x(const TIn* __restrict__ X, int64_t ldx,
   return (row < n && col < ncols) ? (double)X[col * ldx + row] : 0.0;
 }
 
-template <int C, int WR, int WC, typename TIn>
+template <int C, int WR, int WC, int D, typename TIn>
 __global__ __launch_bounds__(64 * WR * WC) void k_trsm(const JobTable tab) {
   constexpr int RW = NB / WR, RT = RW / 16;
   constexpr int CW = C / WC, CT = CW / 16;
   constexpr int CTS = C / 16;  // column tiles per slab
+  constexpr int NPB = NB / 8;  // k-step pairs per row block
   static_assert(RT >= 1 && CT >= 1, "tile shape");
+  static_assert(NPB % D == 0, "prefetch depth must divide the pairs of a block");
   __shared__ __attribute__((aligned(16))) double Rl[NB * C];
 
   // find the job of this slab
@@ -320,31 +322,62 @@ __global__ __launch_bounds__(64 * WR * WC) void k_trsm(const JobTable tab) {
   const int64_t col_base = slab * C + wc * CW;
 
   for (int k = 0; k < K; k++) {
+    // this block's right-hand side, loaded early (consumed after the GEMM)
+    double xv[RT][CT][4];
+#pragma unroll
+    for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+      for (int ct = 0; ct < CT; ct++)
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+          xv[rt][ct][i] = load_x<TIn>(X, ldx, (int64_t)k * NB + wr * RW + rt * 16 + lane / 16 + 4 * i,
+                                      col_base + ct * 16 + lane % 16, n, ncols);
+
     d4 acc[RT][CT];
 #pragma unroll
     for (int a = 0; a < RT; a++)
 #pragma unroll
       for (int b = 0; b < CT; b++) acc[a][b] = (d4){0, 0, 0, 0};
 
-    // R_k accumulation over the previous row blocks
+    // sum_{j<k} L_kj W_j: software pipeline with D k-step pairs in flight
     const double* __restrict__ Ls = Lstrips + strip_offset(k) + (size_t)(wr * RT) * 128 + lane * 2;
     const double* __restrict__ Wb = Wslab + (size_t)(wc * CT) * 128 + lane * 2;
-    const int npairs = k * (NB / 8);
-    for (int kp = 0; kp < npairs; kp++) {
-      d2 a[RT], b[CT];
+    const int npairs = k * NPB;
+    if (npairs > 0) {
+      d2 a[D][RT], b[D][CT];
 #pragma unroll
-      for (int rt = 0; rt < RT; rt++)
-        a[rt] = *reinterpret_cast<const d2*>(Ls + ((size_t)kp * (NB / 16) + rt) * 128);
+      for (int s = 0; s < D; s++) {
 #pragma unroll
-      for (int ct = 0; ct < CT; ct++)
-        b[ct] = *reinterpret_cast<const d2*>(Wb + ((size_t)kp * CTS + ct) * 128);
+        for (int rt = 0; rt < RT; rt++)
+          a[s][rt] = *reinterpret_cast<const d2*>(Ls + ((size_t)s * (NB / 16) + rt) * 128);
 #pragma unroll
-      for (int rt = 0; rt < RT; rt++)
+        for (int ct = 0; ct < CT; ct++)
+          b[s][ct] = *reinterpret_cast<const d2*>(Wb + ((size_t)s * CTS + ct) * 128);
+      }
+      for (int kp0 = 0; kp0 < npairs; kp0 += D) {
 #pragma unroll
-        for (int ct = 0; ct < CT; ct++) {
-          acc[rt][ct] = MFMA64(a[rt].x, b[ct].x, acc[rt][ct]);
-          acc[rt][ct] = MFMA64(a[rt].y, b[ct].y, acc[rt][ct]);
+        for (int s = 0; s < D; s++) {
+#pragma unroll
+          for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+            for (int ct = 0; ct < CT; ct++) {
+              acc[rt][ct] = MFMA64(a[s][rt].x, b[s][ct].x, acc[rt][ct]);
+              acc[rt][ct] = MFMA64(a[s][rt].y, b[s][ct].y, acc[rt][ct]);
+            }
+          // refill this stage with pair kp0 + s + D (clamped to the last
+          // pair; the clamped tail loads are never used)
+          int nx = kp0 + s + D;
+          nx = nx < npairs ? nx : npairs - 1;
+#pragma unroll
+          for (int rt = 0; rt < RT; rt++)
+            a[s][rt] = *reinterpret_cast<const d2*>(Ls + ((size_t)nx * (NB / 16) + rt) * 128);
+#pragma unroll
+          for (int ct = 0; ct < CT; ct++)
+            b[s][ct] = *reinterpret_cast<const d2*>(Wb + ((size_t)nx * CTS + ct) * 128);
+          // keep the refill loads issued here, D stages ahead of their use
+          asm volatile("" ::: "memory");
         }
+      }
     }
 
     // R_k = X_k - acc, staged in LDS in the B-operand pair layout
@@ -353,18 +386,11 @@ __global__ __launch_bounds__(64 * WR * WC) void k_trsm(const JobTable tab) {
       const int rowl = wr * RW + rt * 16;  // row of the tile within the block
 #pragma unroll
       for (int ct = 0; ct < CT; ct++) {
-        const int64_t col = col_base + ct * 16 + lane % 16;
-        double r[4];
-#pragma unroll
-        for (int i = 0; i < 4; i++) {
-          const int64_t row = (int64_t)k * NB + rowl + lane / 16 + 4 * i;
-          r[i] = load_x<TIn>(X, ldx, row, col, n, ncols) - acc[rt][ct][i];
-        }
 #pragma unroll
         for (int i = 0; i < 4; i += 2) {
           const int kp = (rowl / 4 + i) / 2;
           *reinterpret_cast<d2*>(&Rl[((size_t)kp * CTS + wc * CT + ct) * 128 + lane * 2]) =
-              (d2){r[i], r[i + 1]};
+              (d2){xv[rt][ct][i] - acc[rt][ct][i], xv[rt][ct][i + 1] - acc[rt][ct][i + 1]};
         }
       }
     }
@@ -681,13 +707,18 @@ hipError_t launch_unpack_factor(const double* Lstrips, const double* Ldiag, int6
   return hipGetLastError();
 }
 
-hipError_t launch_trsm_i8(const JobTable& tab, int64_t nslabs, hipStream_t st) {
-  k_trsm<TRSM_C, TRSM_WR, TRSM_WC, int8_t><<<(unsigned)nslabs, 64 * TRSM_WR * TRSM_WC, 0, st>>>(tab);
+hipError_t launch_trsm_i8(const JobTable& tab, int64_t nslabs, int C, hipStream_t st) {
+  switch (C) {
+    case 16: k_trsm<16, 4, 1, TRSM_DEPTH, int8_t><<<(unsigned)nslabs, 256, 0, st>>>(tab); break;
+    case 32: k_trsm<32, 4, 2, TRSM_DEPTH, int8_t><<<(unsigned)nslabs, 512, 0, st>>>(tab); break;
+    case 64: k_trsm<64, 4, 2, TRSM_DEPTH, int8_t><<<(unsigned)nslabs, 512, 0, st>>>(tab); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_trsm_f64(const JobTable& tab, int64_t nslabs, hipStream_t st) {
-  k_trsm<TRSM_C, TRSM_WR, TRSM_WC, double><<<(unsigned)nslabs, 64 * TRSM_WR * TRSM_WC, 0, st>>>(tab);
+  k_trsm<FIXED_C, 4, 1, 4, double><<<(unsigned)nslabs, 256, 0, st>>>(tab);
   return hipGetLastError();
 }
 
@@ -701,14 +732,14 @@ hipError_t launch_pack_fixed(const double* XL, int64_t ldx, const double* Y, int
 hipError_t launch_slab_to_rowmajor(const double* W, int64_t n_pad, int ncols, double* F,
                                    hipStream_t st) {
   const int64_t total = n_pad * ncols;
-  k_slab_to_rowmajor<<<(unsigned)((total + 255) / 256), 256, 0, st>>>(W, TRSM_C, n_pad, ncols, F);
+  k_slab_to_rowmajor<<<(unsigned)((total + 255) / 256), 256, 0, st>>>(W, FIXED_C, n_pad, ncols, F);
   return hipGetLastError();
 }
 
-hipError_t launch_slab_to_colmajor(const double* W, int64_t n_pad, int64_t n, int64_t col0,
+hipError_t launch_slab_to_colmajor(const double* W, int C, int64_t n_pad, int64_t n, int64_t col0,
                                    int64_t ncols, double* out, int64_t ldo, hipStream_t st) {
   dim3 grid((unsigned)((n + 255) / 256), (unsigned)(ncols < 65535 ? ncols : 65535));
-  k_slab_to_colmajor<<<grid, 256, 0, st>>>(W, TRSM_C, n_pad, n, col0, ncols, out, ldo);
+  k_slab_to_colmajor<<<grid, 256, 0, st>>>(W, C, n_pad, n, col0, ncols, out, ldo);
   return hipGetLastError();
 }
 

@@ -30,7 +30,7 @@ GLS_OK, GLS_E_NOT_SPD, GLS_E_STATE, GLS_E_OOM, GLS_E_HIP, GLS_E_UNSUPPORTED = 0,
 EXPORTS = ("gls_factor", "gls_whiten_fixed", "gls_solve_block", "gls_reserve", "gls_free",
            "gls_fork", "gls_set_stream", "gls_footprint_bytes", "gls_last_info",
            "gls_strerror", "gls_copy_factor", "gls_copy_fixed", "gls_whiten_block",
-           "gls_solve_multi")
+           "gls_solve_multi", "gls_set_slab_cols", "gls_set_kernel_timing", "gls_kernel_time")
 
 _i64, _p, _int = ctypes.c_int64, ctypes.c_void_p, ctypes.c_int
 
@@ -70,6 +70,10 @@ def lib() -> ctypes.CDLL:
             "gls_copy_fixed": (_int, [_p, _p, _i64, _p, _i64, _p, _p]),
             "gls_whiten_block": (_int, [_p, _i64, _p, _i64, _p, _i64]),
             "gls_solve_multi": (_int, [ctypes.POINTER(gls_work), _i64, _p]),
+            "gls_set_slab_cols": (_int, [_p, _int]),
+            "gls_set_kernel_timing": (_int, [_p, _int]),
+            "gls_kernel_time": (_int, [_p, _int, ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(_i64)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -153,6 +157,20 @@ def gls_whiten_block(h, ncols, X, ldx, W, ldw) -> int:
 def gls_solve_multi(items, stream) -> int:
     arr = (gls_work * len(items))(*items)
     return lib().gls_solve_multi(arr, len(items), stream)
+
+
+def gls_set_slab_cols(h, cols) -> int:
+    return lib().gls_set_slab_cols(h, cols)
+
+
+def gls_set_kernel_timing(h, enable) -> int:
+    return lib().gls_set_kernel_timing(h, enable)
+
+
+def gls_kernel_time(h, kind) -> Tuple[int, float, int]:
+    ms, cnt = ctypes.c_double(), _i64()
+    rc = lib().gls_kernel_time(h, kind, ctypes.byref(ms), ctypes.byref(cnt))
+    return rc, ms.value, cnt.value
 
 
 # ---- torch convenience ---------------------------------------------------------
@@ -267,6 +285,17 @@ class Cohort:
         _chk(gls_copy_fixed(self.h, WL.data_ptr(), n, Yt.data_ptr(), n, STL.data_ptr(),
                             CT.data_ptr()), "gls_copy_fixed")
         return WL, Yt, STL, CT
+
+    def set_slab_cols(self, cols: int):
+        _chk(gls_set_slab_cols(self.h, cols), "gls_set_slab_cols")
+
+    def set_kernel_timing(self, enable: bool):
+        _chk(gls_set_kernel_timing(self.h, int(enable)), "gls_set_kernel_timing")
+
+    def kernel_time(self, kind: int) -> Tuple[float, int]:
+        rc, ms, cnt = gls_kernel_time(self.h, kind)
+        _chk(rc, "gls_kernel_time")
+        return ms, cnt
 
     def fork(self, stream=None) -> "Cohort":
         torch = _torch()

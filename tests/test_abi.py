@@ -23,7 +23,7 @@ def declared_functions():
 
 def test_exports_every_declared_symbol():
     names = declared_functions()
-    assert len(names) >= 14
+    assert len(names) >= 17
     L = gls.lib()
     for name in names:
         assert hasattr(L, name), name
@@ -55,6 +55,9 @@ def test_argument_validation_without_device():
     assert L.gls_solve_multi(None, -1, None) == -2
     assert L.gls_solve_multi(None, 0, None) == 0
     assert L.gls_solve_multi(None, 3, None) == -1
+    assert L.gls_set_slab_cols(None, 64) == -1
+    assert L.gls_set_kernel_timing(None, 1) == -1
+    assert L.gls_kernel_time(None, 0, None, None) == -1
     L.gls_free(None)
 
 
@@ -72,7 +75,7 @@ def test_footprint_arithmetic():
     npad = K * 128
     expect = (K * (K - 1) // 2 * 128 * 128 * 8 + 2 * K * 128 * 128 * 8
               + npad * npad * 8 + K * 128 * 128 * 8
-              + n * (pL + t) * 8 + npad * 64 * 8 + npad * (pL + t) * 8 + (pL + t) ** 2 * 8
+              + n * (pL + t) * 8 + npad * 16 * 8 + npad * (pL + t) * 8 + (pL + t) ** 2 * 8
               + npad * 4096 * 8)
     assert L.gls_footprint_bytes(n, pL, t, cols, 0) == expect
     assert L.gls_footprint_bytes(n, pL, t, cols, 1) > expect
