@@ -4,8 +4,9 @@ One step = one whole pass of the in-core algorithm (Sec. 2, Alg. 5) over
 the throughput workload: factor M (n = 10,000), whiten X_L and y, then solve
 m = 1,000,000 single-SNP problems (p = 4) in blocks of 4096 SNPs, every
 input resident in HBM before the clock starts.  Blocks are distributed
-round-robin over `--streams` handles that share the factor (gls_fork), so
-consecutive blocks overlap on the device.
+`--batch` at a time to one launch (gls_solve_multi over handles that share
+the factor through gls_fork, each with its own workspace), so a single
+launch fills the chip.
 
 Prints ONE JSON line (see the fields below); progress goes to stderr.
 
@@ -46,11 +47,26 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--m", type=int, default=None, help="problems per step (default: workload m)")
     ap.add_argument("--block", type=int, default=None, help="SNPs per solve call (default 4096)")
-    ap.add_argument("--streams", type=int, default=4)
+    ap.add_argument("--streams", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=4, help="blocks whitened per launch")
     ap.add_argument("--slab-cols", type=int, default=64)
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="budget of the oracle's CPU sample (0 skips it)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (for scaling HBM counters)")
     return ap.parse_args()
+
+
+def copy_calibration():
+    """A plain copy of a known size (1 GiB read + 1 GiB written), run under
+    rocprofv3 --pmc to scale FETCH_SIZE / WRITE_SIZE readings."""
+    import torch
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": src.numel() * 8, "dispatches": 3}))
 
 
 def upload_genotypes(torch, w, m):
@@ -73,29 +89,39 @@ def upload_genotypes(torch, w, m):
 
 
 def run_step(gls, torch, dM, dXL, dY, dXR, w, m, block, streams, slab_cols, Bout, info,
-             timing=False):
-    """One full pass: factor, whiten, all blocks.  Returns the handles' kernel times."""
+             timing=False, batch=4):
+    """One full pass: factor, whiten, all blocks.  `batch` blocks of `block`
+    SNPs are whitened by one launch (gls_solve_multi over forked handles,
+    each with its own workspace); launch groups rotate over `streams`.
+    Returns the kernel times recorded by each group's first handle."""
     c = gls.Cohort(dM, stream=streams[0])
     c.set_slab_cols(slab_cols)
     c.whiten_fixed(dXL, dY, intercept_col=0)
-    hs = [c] + [c.fork(s) for s in streams[1:]]
-    for h in hs:
-        h.reserve(block * w.p_R)
+    groups = []
+    for si, s in enumerate(streams):
+        hs = [c if si == 0 and j == 0 else c.fork(s) for j in range(batch)]
+        for h in hs:
+            h.reserve(block * w.p_R)
         if timing:
-            h.set_kernel_timing(True)
+            hs[0].set_kernel_timing(True)
+        groups.append((s, hs))
     nblk = (m + block - 1) // block
-    for b in range(nblk):
-        a, e = b * block, min(m, (b + 1) * block)
-        h = hs[b % len(hs)]
-        with torch.cuda.stream(h.stream):
-            h.solve_block(dXR[:, a * w.p_R:e * w.p_R], p_R=w.p_R, B=Bout[a:e], info=info[a:e])
+    for gi, g0 in enumerate(range(0, nblk, batch)):
+        s, hs = groups[gi % len(groups)]
+        items = []
+        for j, b in enumerate(range(g0, min(nblk, g0 + batch))):
+            a, e = b * block, min(m, (b + 1) * block)
+            items.append((hs[j], dXR[:, a * w.p_R:e * w.p_R], w.p_R, Bout[a:e], info[a:e]))
+        gls.solve_multi(items, stream=s)
     times = None
     if timing:
-        times = [(h.kernel_time(0), h.kernel_time(1)) for h in hs]
+        times = [(hs[0].kernel_time(0), hs[0].kernel_time(1)) for _, hs in groups]
     for s in streams:
         s.synchronize()
-    for h in hs[1:]:
-        h.free()
+    for _, hs in groups:
+        for h in hs:
+            if h is not c:
+                h.free()
     c.free()
     return times
 
@@ -134,6 +160,9 @@ def cpu_baseline(w, M, XL, Y, budget_s):
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         log("bench.py: only --gpus 1 is supported (one GPU per box)")
@@ -160,14 +189,15 @@ def main():
     streams = [torch.cuda.Stream() for _ in range(args.streams)]
 
     for i in range(args.warmup):
-        run_step(gls, torch, dM, dXL, dY, dXR, w, m, block, streams, args.slab_cols, Bout, info)
+        run_step(gls, torch, dM, dXL, dY, dXR, w, m, block, streams, args.slab_cols, Bout, info,
+                 batch=args.batch)
         log(f"warmup step {i} done")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     kt = []
     for i in range(args.steps):
         kt.append(run_step(gls, torch, dM, dXL, dY, dXR, w, m, block, streams, args.slab_cols,
-                           Bout, info, timing=True))
+                           Bout, info, timing=True, batch=args.batch))
         log(f"step {i} done")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -179,6 +209,7 @@ def main():
     trsm_n = sum(t[0][1] for step in kt for t in step)
     asm_ms = sum(t[1][0] for step in kt for t in step)
     asm_n = sum(t[1][1] for step in kt for t in step)
+    # algorithmic work of the triangular solve: n^2 flops per right-hand side
     flops_per_launch = float(w.n) ** 2 * (m * w.p_R) / (trsm_n / args.steps)
     avg_trsm_s = trsm_ms / trsm_n * 1e-3
     achieved = flops_per_launch / avg_trsm_s / 1e12
@@ -190,6 +221,7 @@ def main():
         "kernel": "k_trsm<int8> (FP64 MFMA)", "launches": trsm_n,
         "avg_launch_ms": round(trsm_ms / trsm_n, 4),
         "flops_per_launch": flops_per_launch, "concurrent_streams": args.streams,
+        "blocks_per_launch": args.batch,
         "step_tflops": round(chip_tflops, 3), "step_frac": round(chip_tflops / PEAK_FP64_TFLOPS, 4),
         "assemble_avg_launch_ms": round(asm_ms / max(asm_n, 1), 4),
     }
@@ -208,7 +240,8 @@ def main():
         "higher_is_better": True, "scaling": "weak",
         "vs_baseline": round(value / PAPER_BI_PER_S, 2), "dtype": "f64", "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "p": w.p, "p_L": w.p_L, "p_R": w.p_R, "t": w.t,
-                   "m": m, "block": block, "streams": args.streams, "slab_cols": args.slab_cols,
+                   "m": m, "block": block, "blocks_per_launch": args.batch, "streams": args.streams,
+                   "slab_cols": args.slab_cols,
                    "M": f"h*ZZ^T/q+(1-h)I+1e-3I, q={w.q}, h={w.h}", "parallelism": "1 GPU"},
         "roofline": roofline, "cpu_baseline": cpu,
         "baseline_note": "vs_baseline divides by the paper's 12-core CPU rate for the same "
