@@ -57,6 +57,24 @@ def parse():
     return ap.parse_args()
 
 
+def measured_traffic(batch, slab_cols):
+    """HBM bytes per launch of the FP64 triangular-solve kernel from the
+    committed rocprofv3 counter summary, or None if the kernel source has
+    changed since the counters were taken (or the launch shape differs)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "trsm_fp64_n10000_traffic.md")
+    src = os.path.join(ROOT, "paper_1210_7325_amd", "csrc", "gls_kernels.hip")
+    try:
+        kv = dict(l.split(": ", 1) for l in open(path).read().splitlines() if ": " in l)
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if kv.get("kernel_source_sha256") != sha or int(kv["blocks_per_launch"]) != batch \
+                or slab_cols != 64:
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def copy_calibration():
     """A plain copy of a known size (1 GiB read + 1 GiB written), run under
     rocprofv3 --pmc to scale FETCH_SIZE / WRITE_SIZE readings."""
@@ -217,7 +235,8 @@ def main():
     chip_tflops = float(w.n) ** 2 * m * w.p_R * args.steps / dt / 1e12
     roofline = {
         "bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
-        "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
+        "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
+        "traffic": measured_traffic(args.batch, args.slab_cols),
         "kernel": "k_trsm<int8> (FP64 MFMA)", "launches": trsm_n,
         "avg_launch_ms": round(trsm_ms / trsm_n, 4),
         "flops_per_launch": flops_per_launch, "concurrent_streams": args.streams,
