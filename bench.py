@@ -107,12 +107,12 @@ def upload_genotypes(torch, w, m):
 
 
 def run_step(gls, torch, dM, dXL, dY, dXR, w, m, block, streams, slab_cols, Bout, info,
-             timing=False, batch=4):
+             timing=False, batch=4, precision="fp64"):
     """One full pass: factor, whiten, all blocks.  `batch` blocks of `block`
     SNPs are whitened by one launch (gls_solve_multi over forked handles,
     each with its own workspace); launch groups rotate over `streams`.
     Returns the kernel times recorded by each group's first handle."""
-    c = gls.Cohort(dM, stream=streams[0])
+    c = gls.Cohort(dM, precision=precision, stream=streams[0])
     c.set_slab_cols(slab_cols)
     c.whiten_fixed(dXL, dY, intercept_col=0)
     groups = []

@@ -29,11 +29,10 @@ struct Cohort {
   // fixed part
   bool fixed = false;
   int64_t pL = 0, t = 0, icol = -1;
-  double* Xfix = nullptr;      // [X_L | Y] column-major n x (pL+t)
-  double* Wfix = nullptr;      // L^{-1}[X_L | Y], slab layout (one slab)
-  double* F = nullptr;         // row-major n_pad x (pL+t)
+  double* F = nullptr;         // row-major n_pad x (pL+t): [W_L | ytil] = L^{-1}[X_L | Y]
   double* STL = nullptr;       // pL x pL
   double* CT = nullptr;        // pL x t
+  double* Z = nullptr;         // FP32_REFINE: row-major n_pad x (pL+t), M^{-1}[X_L | Y]
 };
 
 }  // namespace
@@ -48,7 +47,10 @@ struct gls_handle_s {
   hipStream_t stream = nullptr;
   int C = DEFAULT_C;           // columns per work-group of the triangular solve
   double* W = nullptr;         // workspace: whitened genotype columns, slab layout
-  int64_t Wcols = 0;           // capacity in columns (multiple of C)
+  int64_t Wcols = 0;           // capacity in columns (multiple of 64)
+  float* W32 = nullptr;        // FP32_REFINE: FP32 copy of W (quad layout)
+  double* shift = nullptr;     // FP32_REFINE: per-column centering shift
+  double* XZ = nullptr;        // FP32_REFINE: per column (x - s)^T Z, MAXP + MAXT wide
   bool timing = false;         // bracket kernel launches with events
   std::vector<TimedLaunch> timed;
   size_t ntimed = 0;
@@ -87,11 +89,10 @@ void cohort_free(Cohort* c) {
   dfree(c->LinvP);
   dfree(c->Ldiag);
   dfree(c->Lstrips32);
-  dfree(c->Xfix);
-  dfree(c->Wfix);
   dfree(c->F);
   dfree(c->STL);
   dfree(c->CT);
+  dfree(c->Z);
   delete c;
 }
 
@@ -104,9 +105,17 @@ int ensure_workspace(gls_handle h, int64_t ncols) {
   if (need <= h->Wcols) return GLS_OK;
   HIPCHK(hipStreamSynchronize(h->stream));
   dfree(h->W);
+  dfree(h->W32);
+  dfree(h->shift);
+  dfree(h->XZ);
   h->Wcols = 0;
   int rc = dalloc(&h->W, (size_t)h->c->n_pad * (size_t)need);
   if (rc) return rc;
+  if (h->c->prec == GLS_FP32_REFINE) {
+    if ((rc = dalloc(&h->W32, (size_t)h->c->n_pad * (size_t)need))) return rc;
+    if ((rc = dalloc(&h->shift, (size_t)need))) return rc;
+    if ((rc = dalloc(&h->XZ, (size_t)need * (MAXP + MAXT)))) return rc;
+  }
   h->Wcols = need;
   return GLS_OK;
 }
@@ -122,7 +131,24 @@ JobDesc make_job(gls_handle h, int64_t slab0, int64_t ncols, const void* X, int6
   j.LinvP = h->c->LinvP;
   j.W = h->W;
   j.K = h->c->K;
+  j.Lstrips32 = h->c->Lstrips32;
+  j.W32 = h->W32;
+  j.shift = h->shift;
   return j;
+}
+
+XzDesc make_xz(gls_handle h, int64_t grp0, int64_t ncols, const int8_t* X, int64_t ldx) {
+  XzDesc x;
+  x.grp0 = grp0;
+  x.n = h->c->n;
+  x.ncols = ncols;
+  x.X = X;
+  x.ldx = ldx;
+  x.Z = h->c->Z;
+  x.shift = h->shift;
+  x.XZ = h->XZ;
+  x.ldf = (int)(h->c->pL + h->c->t);
+  return x;
 }
 
 AsmDesc make_asm(gls_handle h, int64_t grp0, int64_t nsnp, int64_t pR, double* B, int64_t ldb,
@@ -143,6 +169,9 @@ AsmDesc make_asm(gls_handle h, int64_t grp0, int64_t nsnp, int64_t pR, double* B
   a.pL = (int)h->c->pL;
   a.pR = (int)pR;
   a.t = (int)h->c->t;
+  a.shift = h->shift;
+  a.XZ = h->XZ;
+  a.icol = (int)h->c->icol;
   return a;
 }
 
@@ -184,6 +213,53 @@ struct TimedScope {
   ~TimedScope() { end(); }
 };
 
+// Launch the kernels of up to MAX_INLINE_JOBS checked work items (same slab
+// width and precision) on stream st; timing events go through handle th.
+int launch_items(const gls_work* items, int64_t count, hipStream_t st, gls_handle th) {
+  for (int64_t i = 0; i < count; i++) {
+    int rc = ensure_workspace(items[i].h, items[i].nsnp * items[i].p_R);
+    if (rc) return rc;
+  }
+  const int C = items[0].h->C;
+  const bool refine = items[0].h->c->prec == GLS_FP32_REFINE;
+  JobTable tab;
+  AsmTable at;
+  XzTable xt;
+  tab.njobs = at.njobs = xt.njobs = 0;
+  int64_t slabs = 0, groups = 0, xgroups = 0;
+  for (int64_t i = 0; i < count; i++) {
+    const gls_work& w = items[i];
+    if (w.nsnp == 0) continue;
+    const int64_t ncols = w.nsnp * w.p_R;
+    if (refine) {
+      xt.j[xt.njobs++] = make_xz(w.h, xgroups, ncols, w.X_R, w.ldxr);
+      xgroups += (ncols + 15) / 16;
+    }
+    tab.j[tab.njobs++] = make_job(w.h, slabs, ncols, w.X_R, w.ldxr);
+    slabs += (ncols + C - 1) / C;
+    at.j[at.njobs++] = make_asm(w.h, groups, w.nsnp, w.p_R, w.B, w.ldb, w.info);
+    groups += (w.nsnp + 16 / w.p_R - 1) / (16 / w.p_R);
+  }
+  if (tab.njobs == 0) return GLS_OK;
+  hipStream_t keep = th->stream;
+  th->stream = st;  // timing events go to the launch stream
+  hipError_t e = hipSuccess;
+  if (refine) {
+    TimedScope tx(th, 1);
+    e = launch_xz_shift(xt, xgroups, st);
+  }
+  if (e == hipSuccess) {
+    TimedScope t0(th, 0);
+    e = refine ? launch_trsm_mixed(tab, slabs, C, st) : launch_trsm_i8(tab, slabs, C, st);
+  }
+  if (e == hipSuccess) {
+    TimedScope t1(th, 1);
+    e = launch_assemble_solve(at, groups, refine, st);
+  }
+  th->stream = keep;
+  return hip_code(e);
+}
+
 }  // namespace
 
 extern "C" {
@@ -209,10 +285,14 @@ size_t gls_footprint_bytes(int64_t n, int64_t p_L, int64_t t, int64_t max_cols, 
   b += 2 * (size_t)K * NB * NB * 8;                // inverted + plain diagonal blocks
   b += n_pad * n_pad * 8 + (size_t)K * NB * NB * 8;  // factorization work (transient)
   const size_t w = (size_t)(p_L + t);
-  b += n * w * 8 + n_pad * (size_t)round_up((int64_t)w, FIXED_C) * 8 + n_pad * w * 8 +
-       (w * w) * 8;  // fixed part
+  b += n_pad * w * 8 + (w * w) * 8;  // fixed part
   b += n_pad * (size_t)round_up(std::max<int64_t>(max_cols, 1), 64) * 8;  // workspace
-  if (prec == GLS_FP32_REFINE) b += strips_count(K) * 4;
+  if (prec == GLS_FP32_REFINE) {
+    b += strips_count(K) * 4;                                   // FP32 strips
+    b += n_pad * w * 8;                                         // Z
+    const size_t cols = (size_t)round_up(std::max<int64_t>(max_cols, 1), 64);
+    b += n_pad * cols * 4 + cols * 8 + cols * (MAXP + MAXT) * 8;  // W32, shift, XZ
+  }
   return b;
 }
 
@@ -223,7 +303,6 @@ int gls_factor(gls_handle* out, int64_t n, const double* M, int64_t ldm, int pre
   if (!M) return -3;
   if (ldm < n) return -4;
   if (prec != GLS_FP64 && prec != GLS_FP32_REFINE) return -5;
-  if (prec == GLS_FP32_REFINE) return GLS_E_UNSUPPORTED;
 
   Cohort* c = new (std::nothrow) Cohort();
   if (!c) return GLS_E_OOM;
@@ -297,38 +376,22 @@ int gls_whiten_fixed(gls_handle h, int64_t p_L, const double* X_L, int64_t ldx, 
   if (c->prec == GLS_FP32_REFINE && intercept_col < 0) return GLS_E_UNSUPPORTED;
 
   HIPCHK(hipStreamSynchronize(h->stream));
-  dfree(c->Xfix);
-  dfree(c->Wfix);
   dfree(c->F);
   dfree(c->STL);
   dfree(c->CT);
+  dfree(c->Z);
   c->fixed = false;
   const int64_t w = p_L + t;
   int rc;
-  if ((rc = dalloc(&c->Xfix, (size_t)c->n * w))) return rc;
-  const int64_t fix_slabs = (w + FIXED_C - 1) / FIXED_C;
-  if ((rc = dalloc(&c->Wfix, (size_t)c->n_pad * FIXED_C * fix_slabs))) return rc;
   if ((rc = dalloc(&c->F, (size_t)c->n_pad * w))) return rc;
   if ((rc = dalloc(&c->STL, (size_t)p_L * p_L))) return rc;
   if ((rc = dalloc(&c->CT, (size_t)p_L * t))) return rc;
+  if (c->prec == GLS_FP32_REFINE && (rc = dalloc(&c->Z, (size_t)c->n_pad * w))) return rc;
   c->pL = p_L;
   c->t = t;
   c->icol = intercept_col;
-
-  HIPCHK(launch_pack_fixed(X_L, ldx, Y, ldy, c->n, (int)p_L, (int)t, c->Xfix, h->stream));
-  JobTable tab;
-  tab.njobs = 1;
-  tab.j[0].slab0 = 0;
-  tab.j[0].n = c->n;
-  tab.j[0].ncols = w;
-  tab.j[0].X = c->Xfix;
-  tab.j[0].ldx = c->n;
-  tab.j[0].Lstrips = c->Lstrips;
-  tab.j[0].LinvP = c->LinvP;
-  tab.j[0].W = c->Wfix;
-  tab.j[0].K = c->K;
-  HIPCHK(launch_trsm_f64(tab, fix_slabs, h->stream));
-  HIPCHK(launch_slab_to_rowmajor(c->Wfix, c->n_pad, (int)w, c->F, h->stream));
+  HIPCHK(launch_fixed_solve(X_L, ldx, Y, ldy, c->n, c->n_pad, c->K, (int)p_L, (int)t, c->Lstrips,
+                            c->LinvP, c->F, c->Z, h->stream));
   HIPCHK(launch_gram(c->F, c->n, (int)p_L, (int)t, c->STL, c->CT, h->stream));
   c->fixed = true;
   return GLS_OK;
@@ -345,22 +408,8 @@ int gls_solve_block(gls_handle h, int64_t nsnp, int64_t p_R, const int8_t* X_R, 
   int rc = check_block(h, nsnp, p_R, X_R, ldxr, B, ldb, 2);
   if (rc) return rc;
   if (nsnp == 0) return GLS_OK;
-  const int64_t ncols = nsnp * p_R;
-  if ((rc = ensure_workspace(h, ncols))) return rc;
-  JobTable tab;
-  tab.njobs = 1;
-  tab.j[0] = make_job(h, 0, ncols, X_R, ldxr);
-  TimedScope t0(h, 0);
-  HIPCHK(launch_trsm_i8(tab, (ncols + h->C - 1) / h->C, h->C, h->stream));
-  t0.end();
-  AsmTable at;
-  at.njobs = 1;
-  at.j[0] = make_asm(h, 0, nsnp, p_R, B, ldb, info);
-  const int64_t G = 16 / p_R;
-  TimedScope t1(h, 1);
-  HIPCHK(launch_assemble_solve(at, (nsnp + G - 1) / G, h->stream));
-  t1.end();
-  return GLS_OK;
+  gls_work w{h, nsnp, p_R, X_R, ldxr, B, ldb, info};
+  return launch_items(&w, 1, h->stream, h);
 }
 
 int gls_solve_multi(const gls_work* items, int64_t count, void* stream) {
@@ -369,45 +418,20 @@ int gls_solve_multi(const gls_work* items, int64_t count, void* stream) {
   if (!items) return -1;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const int C = items[0].h ? items[0].h->C : DEFAULT_C;
+  const int prec = items[0].h ? items[0].h->c->prec : GLS_FP64;
   for (int64_t i = 0; i < count; i++) {
     const gls_work& w = items[i];
-    if (w.h && w.h->C != C) return GLS_E_UNSUPPORTED;  // one slab width per launch
     int rc = check_block(w.h, w.nsnp, w.p_R, w.X_R, w.ldxr, w.B, w.ldb, 2);
     if (rc) return rc < 0 ? -1 : rc;
+    // one slab width and one precision per launch
+    if (w.h->C != C || w.h->c->prec != prec) return GLS_E_UNSUPPORTED;
     for (int64_t j = 0; j < i; j++)
       if (items[j].h == w.h) return -1;  // each item needs its own workspace
   }
-  for (int64_t i = 0; i < count; i++) {
-    int rc = ensure_workspace(items[i].h, items[i].nsnp * items[i].p_R);
-    if (rc) return rc;
-  }
   for (int64_t a = 0; a < count; a += MAX_INLINE_JOBS) {
     const int64_t b = std::min<int64_t>(count, a + MAX_INLINE_JOBS);
-    JobTable tab;
-    AsmTable at;
-    tab.njobs = at.njobs = 0;
-    int64_t slabs = 0, groups = 0;
-    for (int64_t i = a; i < b; i++) {
-      const gls_work& w = items[i];
-      if (w.nsnp == 0) continue;
-      const int64_t ncols = w.nsnp * w.p_R;
-      tab.j[tab.njobs++] = make_job(w.h, slabs, ncols, w.X_R, w.ldxr);
-      slabs += (ncols + C - 1) / C;
-      at.j[at.njobs++] = make_asm(w.h, groups, w.nsnp, w.p_R, w.B, w.ldb, w.info);
-      groups += (w.nsnp + 16 / w.p_R - 1) / (16 / w.p_R);
-    }
-    if (tab.njobs == 0) continue;
-    gls_handle h0 = items[a].h;
-    hipStream_t keep = h0->stream;
-    h0->stream = st;  // timing events go to the launch stream
-    TimedScope t0(h0, 0);
-    hipError_t e = launch_trsm_i8(tab, slabs, C, st);
-    t0.end();
-    TimedScope t1(h0, 1);
-    if (e == hipSuccess) e = launch_assemble_solve(at, groups, st);
-    t1.end();
-    h0->stream = keep;
-    HIPCHK(e);
+    int rc = launch_items(items + a, b - a, st, items[a].h);
+    if (rc) return rc;
   }
   return GLS_OK;
 }
@@ -432,6 +456,9 @@ void gls_free(gls_handle h) {
   if (!h) return;
   (void)hipStreamSynchronize(h->stream);
   dfree(h->W);
+  dfree(h->W32);
+  dfree(h->shift);
+  dfree(h->XZ);
   for (auto& p : h->timed) {
     if (p.a) (void)hipEventDestroy(p.a);
     if (p.b) (void)hipEventDestroy(p.b);
@@ -456,8 +483,9 @@ int gls_copy_fixed(gls_handle h, double* WL, int64_t ldwl, double* Yt, int64_t l
   if (WL && ldwl < c->n) return -3;
   if (Yt && ldyt < c->n) return -5;
   if (!c->fixed) return GLS_E_STATE;
-  if (WL) HIPCHK(launch_slab_to_colmajor(c->Wfix, FIXED_C, c->n_pad, c->n, 0, c->pL, WL, ldwl, h->stream));
-  if (Yt) HIPCHK(launch_slab_to_colmajor(c->Wfix, FIXED_C, c->n_pad, c->n, c->pL, c->t, Yt, ldyt, h->stream));
+  const int w = (int)(c->pL + c->t);
+  if (WL) HIPCHK(launch_rowmajor_to_colmajor(c->F, w, c->n, 0, (int)c->pL, WL, ldwl, h->stream));
+  if (Yt) HIPCHK(launch_rowmajor_to_colmajor(c->F, w, c->n, (int)c->pL, (int)c->t, Yt, ldyt, h->stream));
   if (S_TL)
     HIPCHK(hipMemcpyAsync(S_TL, c->STL, sizeof(double) * c->pL * c->pL, hipMemcpyDeviceToDevice,
                           h->stream));
@@ -483,7 +511,13 @@ int gls_whiten_block(gls_handle h, int64_t ncols, const int8_t* X, int64_t ldx, 
   tab.njobs = 1;
   tab.j[0] = make_job(h, 0, ncols, X, ldx);
   TimedScope t0(h, 0);
-  HIPCHK(launch_trsm_i8(tab, (ncols + h->C - 1) / h->C, h->C, h->stream));
+  if (h->c->prec == GLS_FP32_REFINE) {
+    // plain L^{-1} X: no centering shift
+    HIPCHK(hipMemsetAsync(h->shift, 0, sizeof(double) * ncols, h->stream));
+    HIPCHK(launch_trsm_mixed(tab, (ncols + h->C - 1) / h->C, h->C, h->stream));
+  } else {
+    HIPCHK(launch_trsm_i8(tab, (ncols + h->C - 1) / h->C, h->C, h->stream));
+  }
   t0.end();
   HIPCHK(launch_slab_to_colmajor(h->W, h->C, h->c->n_pad, h->c->n, 0, ncols, W, ldw, h->stream));
   return GLS_OK;
@@ -492,6 +526,7 @@ int gls_whiten_block(gls_handle h, int64_t ncols, const int8_t* X, int64_t ldx, 
 int gls_set_slab_cols(gls_handle h, int cols) {
   if (!h) return -1;
   if (cols != 16 && cols != 32 && cols != 64) return -2;
+  if (h->c->prec == GLS_FP32_REFINE && cols == 16) return GLS_E_UNSUPPORTED;
   h->C = cols;
   return GLS_OK;
 }

@@ -30,8 +30,10 @@
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef double d2 __attribute__((ext_vector_type(2)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
 #define MFMA64(a, b, c) __builtin_amdgcn_mfma_f64_16x16x4f64((a), (b), (c), 0, 0, 0)
+#define MFMA32(a, b, c) __builtin_amdgcn_mfma_f32_16x16x4f32((a), (b), (c), 0, 0, 0)
 
 namespace gls {
 
@@ -245,7 +247,13 @@ __global__ __launch_bounds__(256) void k_pack(const double* __restrict__ A, int6
       const double v = A[((int64_t)k * NB + row) + ((int64_t)j * NB + colb) * lda];
       const size_t dst = strip_offset(k) + (size_t)j * NB * NB + d;
       Lstrips[dst] = v;
-      if (Lstrips32) Lstrips32[dst] = (float)v;
+      if (Lstrips32) {
+        // FP32 copy in the quad layout: ((kq * (NB/16) + rt) * 64 + lane) * 4 + k-step % 4
+        const int ks = colb / 4, lane32 = (colb % 4) * 16 + row % 16;
+        const size_t dst32 = strip_offset(k) + (size_t)j * NB * NB +
+                             ((size_t)((ks / 4) * (NB / 16) + row / 16) * 64 + lane32) * 4 + ks % 4;
+        Lstrips32[dst32] = (float)v;
+      }
     } else {
       LinvP[(size_t)k * NB * NB + d] = Linv[(size_t)k * NB * NB + row + (size_t)colb * NB];
     }
@@ -445,16 +453,6 @@ __device__ __forceinline__ size_t slab_index(int64_t row, int64_t col, int C, in
          (size_t)(((row % 4) * 16 + cc % 16) * 2 + (ks % 2));
 }
 
-// Slab layout -> row-major n_pad x ld (the fixed part F = [W_L | ytil]).
-__global__ void k_slab_to_rowmajor(const double* __restrict__ W, int C, int64_t n_pad,
-                                   int ncols, double* __restrict__ F) {
-  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= n_pad * ncols) return;
-  int64_t r = idx / ncols;
-  int c = (int)(idx % ncols);
-  F[idx] = W[slab_index(r, c, C, n_pad)];
-}
-
 // Slab layout -> caller's column-major array (inspection).
 __global__ void k_slab_to_colmajor(const double* __restrict__ W, int C, int64_t n_pad, int64_t n,
                                    int64_t col0, int64_t ncols, double* __restrict__ out, int64_t ldo) {
@@ -465,13 +463,105 @@ __global__ void k_slab_to_colmajor(const double* __restrict__ W, int C, int64_t 
   }
 }
 
-// Pack [X_L | Y] (two column-major inputs) into one n x (pL+t) buffer.
+// ---------------------------------------------------------------------------
+// a1: the fixed part F = [X_L | Y] (p_L + t <= 27 columns, once per cohort),
+// row-major n_pad x w.  Triangular solves on it run right-looking with one
+// launch per row block: the diagonal step on block k, then the update of
+// every other affected block in parallel (one work-group per block, the
+// 128 x 128 block of L staged in LDS from its contiguous packed form).
+//   lower (F := L^{-1} F):  F_k = inv(L_kk) F_k;  F_j -= L_jk F_k  (j > k)
+//   upper (Z := L^{-T} Z):  Z_k = inv(L_kk)^T Z_k; Z_j -= L_kj^T Z_k (j < k)
+
+// F (row-major n_pad x w, zero padding) from the two column-major inputs.
 __global__ void k_pack_fixed(const double* __restrict__ XL, int64_t ldx, const double* __restrict__ Y,
-                             int64_t ldy, int64_t n, int pL, int t, double* __restrict__ out) {
+                             int64_t ldy, int64_t n, int64_t n_pad, int pL, int t,
+                             double* __restrict__ F) {
+  const int w = pL + t;
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n_pad * w) return;
+  const int64_t r = idx / w;
+  const int c = (int)(idx % w);
+  double v = 0.0;
+  if (r < n) v = (c < pL) ? XL[r + c * ldx] : Y[r + (c - pL) * ldy];
+  F[idx] = v;
+}
+
+// Unpack a 128 x 128 block stored in the fragment pair layout into T[row][col].
+__device__ __forceinline__ void stage_block(double (*T)[NB + 1], const double* __restrict__ blk) {
+  for (int d = threadIdx.x; d < NB * NB; d += blockDim.x) {
+    const int kk = d & 1, ln = (d >> 1) & 63, rt = (d >> 7) % (NB / 16), kp = (d >> 7) / (NB / 16);
+    T[rt * 16 + ln % 16][(2 * kp + kk) * 4 + ln / 16] = blk[d];
+  }
+}
+
+constexpr int FIX_COLS_PER_THREAD = (MAXP + MAXT + 1) / 2;
+
+// acc[ci] = sum_b op(T)[a][b] * F[(r0 + b) * w + c] over the thread's columns
+// c = half + 2 ci, with op(T) = T (lower) or T^T (upper) and b restricted to
+// the nonzero triangle when `tri` is set.
+template <bool UPPER>
+__device__ __forceinline__ void fix_product(const double (*T)[NB + 1], const double* __restrict__ F,
+                                            int64_t r0, int w, int a, int half, bool tri,
+                                            double (&acc)[FIX_COLS_PER_THREAD]) {
+#pragma unroll
+  for (int ci = 0; ci < FIX_COLS_PER_THREAD; ci++) acc[ci] = 0.0;
+  const int b0 = (tri && UPPER) ? a : 0;
+  const int b1 = (tri && !UPPER) ? a + 1 : NB;
+  for (int b = b0; b < b1; b++) {
+    const double tv = UPPER ? T[b][a] : T[a][b];
+    const double* __restrict__ f = F + (r0 + b) * w;
+#pragma unroll
+    for (int ci = 0; ci < FIX_COLS_PER_THREAD; ci++) {
+      const int c = half + 2 * ci;
+      if (c < w) acc[ci] += tv * f[c];
+    }
+  }
+}
+
+template <bool UPPER>
+__global__ __launch_bounds__(256) void k_fix_diag(const double* __restrict__ LinvP, int k,
+                                                  double* __restrict__ F, int w) {
+  __shared__ double T[NB][NB + 1];
+  stage_block(T, LinvP + (size_t)k * NB * NB);
+  __syncthreads();
+  const int a = threadIdx.x % NB, half = threadIdx.x / NB;
+  double acc[FIX_COLS_PER_THREAD];
+  fix_product<UPPER>(T, F, (int64_t)k * NB, w, a, half, true, acc);
+  __syncthreads();  // every read of block k happens before it is overwritten
+#pragma unroll
+  for (int ci = 0; ci < FIX_COLS_PER_THREAD; ci++) {
+    const int c = half + 2 * ci;
+    if (c < w) F[((int64_t)k * NB + a) * w + c] = acc[ci];
+  }
+}
+
+template <bool UPPER>
+__global__ __launch_bounds__(256) void k_fix_update(const double* __restrict__ Lstrips, int k,
+                                                    double* __restrict__ F, int w) {
+  __shared__ double T[NB][NB + 1];
+  const int j = UPPER ? (int)blockIdx.x : k + 1 + (int)blockIdx.x;
+  // lower: block L_jk (strip j, block column k); upper: block L_kj (strip k, column j)
+  const double* blk = UPPER ? Lstrips + strip_offset(k) + (size_t)j * NB * NB
+                            : Lstrips + strip_offset(j) + (size_t)k * NB * NB;
+  stage_block(T, blk);
+  __syncthreads();
+  const int a = threadIdx.x % NB, half = threadIdx.x / NB;
+  double acc[FIX_COLS_PER_THREAD];
+  fix_product<UPPER>(T, F, (int64_t)k * NB, w, a, half, false, acc);
+#pragma unroll
+  for (int ci = 0; ci < FIX_COLS_PER_THREAD; ci++) {
+    const int c = half + 2 * ci;
+    if (c < w) F[((int64_t)j * NB + a) * w + c] -= acc[ci];
+  }
+}
+
+// Row-major F -> caller's column-major array (inspection).
+__global__ void k_rowmajor_to_colmajor(const double* __restrict__ F, int w, int64_t n, int col0,
+                                       int ncols, double* __restrict__ out, int64_t ldo) {
   int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int c = blockIdx.y;
-  if (r >= n) return;
-  out[r + c * n] = (c < pL) ? XL[r + c * ldx] : Y[r + (c - pL) * ldy];
+  if (r >= n || c >= ncols) return;
+  out[r + c * ldo] = F[r * w + col0 + c];
 }
 
 // S_TL = W_L^T W_L and C_T = W_L^T ytil (syrk / gemv of Alg. 5): one
@@ -510,6 +600,86 @@ __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ F, int6
 // c_i, and wave-wide broadcasts (v_readlane) between the steps.
 constexpr int AS_WAVES = 8;
 
+// Cholesky of a p x p SPD matrix held by one wavefront, lane j holding
+// column j (col[a] = S[a][j]).  On return lane j holds column j of the
+// lower factor G (rows >= j).  fail = order of the first leading minor
+// that is not positive (0 if none).
+__device__ __forceinline__ void wave_cholesky(double (&col)[MAXP], int p, int lane, int& fail) {
+  fail = 0;
+  for (int k = 0; k < p; k++) {
+    double d = 0.0;
+#pragma unroll
+    for (int a = 0; a < MAXP; a++)
+      if (a == k) d = bcast_lane(col[a], k);
+    if (!(d > 0.0) || !(d < INFINITY)) { fail = k + 1; return; }
+    const double gdiag = sqrt(d);
+    if (lane == k) {
+#pragma unroll
+      for (int a = 0; a < MAXP; a++) {
+        if (a > k) col[a] = col[a] / gdiag;
+        else if (a == k) col[a] = gdiag;
+      }
+    }
+    double gk[MAXP];
+    double gmine = 0.0;
+#pragma unroll
+    for (int a = 0; a < MAXP; a++) {
+      gk[a] = (a > k && a < p) ? bcast_lane(col[a], k) : 0.0;
+      if (a == lane) gmine = gk[a];
+    }
+    if (lane > k && lane < p) {
+#pragma unroll
+      for (int a = 0; a < MAXP; a++)
+        if (a >= lane) col[a] -= gk[a] * gmine;
+    }
+  }
+}
+
+// Solve G G^T x = r in place (r: lane j holds row j, t columns), G from
+// wave_cholesky: forward substitution G z = r, then backward G^T x = z.
+__device__ __forceinline__ void wave_cholsolve(const double (&col)[MAXP], double (&r)[MAXT], int p,
+                                               int t, int lane) {
+  for (int k = 0; k < p; k++) {
+    double gkk = 0.0, gmine = 0.0;
+#pragma unroll
+    for (int a = 0; a < MAXP; a++) {
+      if (a == k) gkk = bcast_lane(col[a], k);
+      const double g = (a > k && a < p) ? bcast_lane(col[a], k) : 0.0;
+      if (a == lane) gmine = g;
+    }
+#pragma unroll
+    for (int j = 0; j < MAXT; j++) {
+      if (j < t) {
+        const double zk = bcast_lane(r[j], k) / gkk;
+        if (lane == k) r[j] = zk;
+        else if (lane > k && lane < p) r[j] -= gmine * zk;
+      }
+    }
+  }
+  for (int k = p - 1; k >= 0; k--) {
+    double gkk = 0.0, gki = 0.0;
+#pragma unroll
+    for (int a = 0; a < MAXP; a++)
+      if (a == k) { gkk = bcast_lane(col[a], k); gki = col[a]; }
+#pragma unroll
+    for (int j = 0; j < MAXT; j++) {
+      if (j < t) {
+        const double bk = bcast_lane(r[j], k) / gkk;
+        if (lane == k) r[j] = bk;
+        else if (lane < k) r[j] -= gki * bk;
+      }
+    }
+  }
+}
+
+// REFINE = false: the FP64 path.  REFINE = true: the FP32_REFINE form; the
+// whitened columns are those of the centered genotypes x' = x - s, S^(0) and
+// c^(0) come from them, and one FP64 refinement step on the normal
+// equations uses S' = [S_TL, E^T; E, S^(0)_BR], c' = [C_T; e_y] with
+// E = x'^T Z_L and e_y = x'^T Z_y exact to FP64 rounding (Z = M^{-1}[X_L|Y]):
+//   r = c' - S' b0,  d = (G G^T)^{-1} r,  b' = b0 + d,
+// then b_L[icol] -= s^T b'_R undoes the centering.
+template <bool REFINE>
 __global__ __launch_bounds__(64 * AS_WAVES) void k_assemble_solve(const AsmTable tab) {
   __shared__ double red[AS_WAVES][16][MAXP + MAXT + 16];
   __shared__ double Ssh[16][MAXP * MAXP];
@@ -531,7 +701,6 @@ __global__ __launch_bounds__(64 * AS_WAVES) void k_assemble_solve(const AsmTable
   const int q = valid ? cl % pR : 0;
   const int first = rg * 16 + (valid ? cl - q : 0);
   const int ldf = pL + t;
-  const int nR = pL + t + pR;
 
   double acc[MAXP + MAXT + 16];
 #pragma unroll
@@ -571,7 +740,7 @@ __global__ __launch_bounds__(64 * AS_WAVES) void k_assemble_solve(const AsmTable
       if (e < pR) red[wave][cl][ldf + e] = acc[MAXP + MAXT + e];
   }
   __syncthreads();
-  // assemble S_i and c_i for the ng problems
+  // assemble S_i and c_i for the ng problems (Fig. 1)
   for (int idx = threadIdx.x; idx < ng * p * p; idx += 64 * AS_WAVES) {
     const int g = idx / (p * p), a = (idx % (p * p)) % p, b = (idx % (p * p)) / p;
     double v;
@@ -612,54 +781,42 @@ __global__ __launch_bounds__(64 * AS_WAVES) void k_assemble_solve(const AsmTable
 #pragma unroll
     for (int j = 0; j < MAXT; j++) crow[j] = (lane < p && j < t) ? Csh[g][lane + j * p] : 0.0;
     int fail = 0;
-    for (int k = 0; k < p; k++) {
-      double d = 0.0;
-#pragma unroll
-      for (int a = 0; a < MAXP; a++)
-        if (a == k) d = bcast_lane(col[a], k);
-      if (!(d > 0.0) || !(d < INFINITY)) { fail = k + 1; break; }
-      const double gdiag = sqrt(d);
-      if (lane == k) {
-#pragma unroll
-        for (int a = 0; a < MAXP; a++) {
-          if (a > k) col[a] = col[a] / gdiag;
-          else if (a == k) col[a] = gdiag;
-        }
-      }
-      double gk[MAXP];
-      double gmine = 0.0;
-#pragma unroll
-      for (int a = 0; a < MAXP; a++) {
-        gk[a] = (a > k && a < p) ? bcast_lane(col[a], k) : 0.0;
-        if (a == lane) gmine = gk[a];
-      }
-      if (lane > k && lane < p) {
-#pragma unroll
-        for (int a = 0; a < MAXP; a++)
-          if (a >= lane) col[a] -= gk[a] * gmine;
-      }
-      // forward substitution step with the new column of the factor
-#pragma unroll
-      for (int j = 0; j < MAXT; j++) {
-        if (j < t) {
-          const double zk = bcast_lane(crow[j], k) / gdiag;
-          if (lane == k) crow[j] = zk;
-          else if (lane > k && lane < p) crow[j] -= gmine * zk;
-        }
-      }
-    }
+    wave_cholesky(col, p, lane, fail);
     if (!fail) {
-      for (int k = p - 1; k >= 0; k--) {
-        double gkk = 0.0, gki = 0.0;
+      wave_cholsolve(col, crow, p, t, lane);
+      if (REFINE) {
+        // residual of the normal equations with the FP64-exact blocks
+        const int64_t cbase = col0 + (int64_t)g * pR;  // first genotype column of the problem
+        double r[MAXT];
 #pragma unroll
-        for (int a = 0; a < MAXP; a++)
-          if (a == k) { gkk = bcast_lane(col[a], k); gki = col[a]; }
+        for (int j = 0; j < MAXT; j++) {
+          r[j] = 0.0;
+          if (j < t) {
+            double v = 0.0;
+            if (lane < pL) v = J.CT[lane + j * pL];
+            else if (lane < p) v = J.XZ[(cbase + lane - pL) * ldf + pL + j];
+            for (int b = 0; b < p; b++) {
+              const double bb = bcast_lane(crow[j], b);
+              double sab = 0.0;
+              if (lane < pL && b < pL) sab = J.STL[lane + b * pL];
+              else if (lane < pL && b < p) sab = J.XZ[(cbase + b - pL) * ldf + lane];
+              else if (lane < p && b < pL) sab = J.XZ[(cbase + lane - pL) * ldf + b];
+              else if (lane < p && b < p) sab = Ssh[g][lane + b * p];
+              v -= sab * bb;
+            }
+            r[j] = lane < p ? v : 0.0;
+          }
+        }
+        wave_cholsolve(col, r, p, t, lane);
+#pragma unroll
+        for (int j = 0; j < MAXT; j++) crow[j] += r[j];
+        // undo the centering: b_L[icol] -= sum_q s_q b'_R[q]
 #pragma unroll
         for (int j = 0; j < MAXT; j++) {
           if (j < t) {
-            const double bk = bcast_lane(crow[j], k) / gkk;
-            if (lane == k) crow[j] = bk;
-            else if (lane < k) crow[j] -= gki * bk;
+            double corr = 0.0;
+            for (int qq = 0; qq < pR; qq++) corr += J.shift[cbase + qq] * bcast_lane(crow[j], pL + qq);
+            if (lane == J.icol) crow[j] -= corr;
           }
         }
       }
@@ -671,6 +828,259 @@ __global__ __launch_bounds__(64 * AS_WAVES) void k_assemble_solve(const AsmTable
         if (j < t) J.B[(i * t + j) * J.ldb + lane] = fail ? NAN : crow[j];
     }
     if (lane == 0 && J.info) J.info[i] = fail;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a5: FP32_REFINE form
+
+// Centering pre-pass: per genotype column the exact dyadic shift
+// s = round(256 * mean(x)) / 256 (x - s is exact in FP32: at most 10
+// significant bits) and (x - s)^T Z with Z = M^{-1}[X_L | Y].
+__global__ __launch_bounds__(64 * AS_WAVES) void k_xz_shift(const XzTable tab) {
+  __shared__ int isum[AS_WAVES][16];
+  __shared__ double sh[16];
+  __shared__ double red[AS_WAVES][16][MAXP + MAXT];
+  int jb = 0;
+  while (jb + 1 < tab.njobs && (int64_t)blockIdx.x >= tab.j[jb + 1].grp0) jb++;
+  const XzDesc& J = tab.j[jb];
+  const int64_t col0 = ((int64_t)blockIdx.x - J.grp0) * 16;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int rg = lane / 16, cl = lane % 16;
+  const bool valid = col0 + cl < J.ncols;
+  const int64_t col = valid ? col0 + cl : col0;
+  const int8_t* __restrict__ x = J.X + col * J.ldx;
+  const int64_t nsteps = (J.n + 3) / 4;
+  int s = 0;
+  for (int64_t st = wave; st < nsteps; st += AS_WAVES) {
+    const int64_t row = 4 * st + rg;
+    if (valid && row < J.n) s += x[row];
+  }
+  s += __shfl_xor(s, 16);
+  s += __shfl_xor(s, 32);
+  if (rg == 0) isum[wave][cl] = s;
+  __syncthreads();
+  if (threadIdx.x < 16) {
+    int tot = 0;
+    for (int w = 0; w < AS_WAVES; w++) tot += isum[w][threadIdx.x];
+    const double shift = rint(256.0 * (double)tot / (double)J.n) / 256.0;
+    sh[threadIdx.x] = shift;
+    if (col0 + threadIdx.x < J.ncols) J.shift[col0 + threadIdx.x] = shift;
+  }
+  __syncthreads();
+  const double sft = sh[cl];
+  const int ldf = J.ldf;
+  double acc[MAXP + MAXT];
+#pragma unroll
+  for (int e = 0; e < MAXP + MAXT; e++) acc[e] = 0.0;
+  for (int64_t st = wave; st < nsteps; st += AS_WAVES) {
+    const int64_t row = 4 * st + rg;
+    const double xv = (valid && row < J.n) ? (double)x[row] - sft : 0.0;
+    const double* __restrict__ z = J.Z + row * ldf;
+#pragma unroll
+    for (int e = 0; e < MAXP + MAXT; e++)
+      if (e < ldf) acc[e] += xv * z[e];
+  }
+#pragma unroll
+  for (int e = 0; e < MAXP + MAXT; e++) {
+    double v = acc[e];
+    v += __shfl_xor(v, 16);
+    v += __shfl_xor(v, 32);
+    acc[e] = v;
+  }
+  if (rg == 0) {
+#pragma unroll
+    for (int e = 0; e < MAXP + MAXT; e++)
+      if (e < ldf) red[wave][cl][e] = acc[e];
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < 16 * ldf; idx += 64 * AS_WAVES) {
+    const int c = idx / ldf, e = idx % ldf;
+    if (col0 + c < J.ncols) {
+      double v = 0.0;
+      for (int w = 0; w < AS_WAVES; w++) v += red[w][c][e];
+      J.XZ[(col0 + c) * ldf + e] = v;
+    }
+  }
+}
+
+// Mixed-precision blocked lower solve W = L^{-1}(X - 1 s^T): as k_trsm, but
+// each off-diagonal product L_kj W_j uses FP32-rounded operands on FP32 MFMA
+// (v_mfma_f32_16x16x4f32) with FP32 accumulation over one chunk of CHQ
+// k-step quads (4 k-steps each; CHQ = NB/16 is one whole diagonal block),
+// and the chunk is added into an FP64 running accumulator.  The diagonal
+// step inv(L_kk) R_k stays FP64.  Both W (FP64, for the assembly) and an
+// FP32 copy (quad layout, for later trailing products) are stored.
+// The FP32 output layout is lane l, element i -> row 4(l/16) + i.
+template <int C, int WR, int WC, int D, int CHQ>
+__global__ __launch_bounds__(64 * WR * WC) void k_trsm_mixed(const JobTable tab) {
+  constexpr int RW = NB / WR, RT = RW / 16;
+  constexpr int CW = C / WC, CT = CW / 16;
+  constexpr int CTS = C / 16;
+  constexpr int NQB = NB / 16;  // k-step quads per row block
+  static_assert(NQB % CHQ == 0 && (CHQ % D == 0 || D % CHQ == 0), "chunking");
+  __shared__ __attribute__((aligned(16))) double Rl[NB * C];
+
+  int jb = 0;
+  while (jb + 1 < tab.njobs && (int64_t)blockIdx.x >= tab.j[jb + 1].slab0) jb++;
+  const JobDesc& J = tab.j[jb];
+  const int64_t slab = (int64_t)blockIdx.x - J.slab0;
+  const int K = J.K;
+  const int64_t n = J.n, ncols = J.ncols;
+  const int8_t* __restrict__ X = reinterpret_cast<const int8_t*>(J.X);
+  const int64_t ldx = J.ldx;
+  const double* __restrict__ shift = J.shift;
+  const float* __restrict__ L32 = J.Lstrips32;
+  const double* __restrict__ LinvP = J.LinvP;
+  double* __restrict__ Wslab = J.W + slab * (int64_t)K * NB * C;
+  float* __restrict__ W32slab = J.W32 + slab * (int64_t)K * NB * C;
+
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int wr = wave / WC, wc = wave % WC;
+  const int64_t col_base = slab * C + wc * CW;
+
+  for (int k = 0; k < K; k++) {
+    double xv[RT][CT][4];
+#pragma unroll
+    for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+      for (int ct = 0; ct < CT; ct++) {
+        const int64_t col = col_base + ct * 16 + lane % 16;
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+          const int64_t row = (int64_t)k * NB + wr * RW + rt * 16 + 4 * (lane / 16) + i;
+          xv[rt][ct][i] = (row < n && col < ncols) ? (double)X[col * ldx + row] - shift[col] : 0.0;
+        }
+      }
+
+    d4 acc[RT][CT];
+    f4 c32[RT][CT];
+#pragma unroll
+    for (int a = 0; a < RT; a++)
+#pragma unroll
+      for (int b = 0; b < CT; b++) {
+        acc[a][b] = (d4){0, 0, 0, 0};
+        c32[a][b] = (f4){0, 0, 0, 0};
+      }
+
+    const float* __restrict__ Ls = L32 + strip_offset(k) + (size_t)(wr * RT) * 256 + lane * 4;
+    const float* __restrict__ Wb = W32slab + (size_t)(wc * CT) * 256 + lane * 4;
+    const int nq = k * NQB;
+    if (nq > 0) {
+      f4 a[D][RT], b[D][CT];
+#pragma unroll
+      for (int s = 0; s < D; s++) {
+#pragma unroll
+        for (int rt = 0; rt < RT; rt++)
+          a[s][rt] = *reinterpret_cast<const f4*>(Ls + ((size_t)s * (NB / 16) + rt) * 256);
+#pragma unroll
+        for (int ct = 0; ct < CT; ct++)
+          b[s][ct] = *reinterpret_cast<const f4*>(Wb + ((size_t)s * CTS + ct) * 256);
+      }
+      for (int q0 = 0; q0 < nq; q0 += D) {
+#pragma unroll
+        for (int s = 0; s < D; s++) {
+#pragma unroll
+          for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+            for (int ct = 0; ct < CT; ct++) {
+              c32[rt][ct] = MFMA32(a[s][rt].x, b[s][ct].x, c32[rt][ct]);
+              c32[rt][ct] = MFMA32(a[s][rt].y, b[s][ct].y, c32[rt][ct]);
+              c32[rt][ct] = MFMA32(a[s][rt].z, b[s][ct].z, c32[rt][ct]);
+              c32[rt][ct] = MFMA32(a[s][rt].w, b[s][ct].w, c32[rt][ct]);
+            }
+          int nx = q0 + s + D;
+          nx = nx < nq ? nx : nq - 1;
+#pragma unroll
+          for (int rt = 0; rt < RT; rt++)
+            a[s][rt] = *reinterpret_cast<const f4*>(Ls + ((size_t)nx * (NB / 16) + rt) * 256);
+#pragma unroll
+          for (int ct = 0; ct < CT; ct++)
+            b[s][ct] = *reinterpret_cast<const f4*>(Wb + ((size_t)nx * CTS + ct) * 256);
+          asm volatile("" ::: "memory");
+          if (CHQ <= D && (s + 1) % CHQ == 0) {
+            // end of an FP32 chunk: fold into the FP64 running sum
+#pragma unroll
+            for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+              for (int ct = 0; ct < CT; ct++) {
+#pragma unroll
+                for (int i = 0; i < 4; i++) acc[rt][ct][i] += (double)c32[rt][ct][i];
+                c32[rt][ct] = (f4){0, 0, 0, 0};
+              }
+          }
+        }
+        if (CHQ > D && (q0 + D) % CHQ == 0) {
+#pragma unroll
+          for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+            for (int ct = 0; ct < CT; ct++) {
+#pragma unroll
+              for (int i = 0; i < 4; i++) acc[rt][ct][i] += (double)c32[rt][ct][i];
+              c32[rt][ct] = (f4){0, 0, 0, 0};
+            }
+        }
+      }
+    }
+
+    // R_k = (x - s) - acc, to LDS in the FP64 B-operand pair layout: element
+    // (row 4g + i) of the FP32 output goes to k-step (row0/4 + g), lane 16i + l%16
+#pragma unroll
+    for (int rt = 0; rt < RT; rt++) {
+      const int rowl = wr * RW + rt * 16;
+      const int ks = rowl / 4 + lane / 16;
+#pragma unroll
+      for (int ct = 0; ct < CT; ct++)
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+          Rl[((size_t)(ks / 2) * CTS + wc * CT + ct) * 128 + (i * 16 + lane % 16) * 2 + (ks % 2)] =
+              xv[rt][ct][i] - acc[rt][ct][i];
+    }
+    __syncthreads();
+
+    d4 w64[RT][CT];
+#pragma unroll
+    for (int a = 0; a < RT; a++)
+#pragma unroll
+      for (int b = 0; b < CT; b++) w64[a][b] = (d4){0, 0, 0, 0};
+    const double* __restrict__ Li = LinvP + (size_t)k * NB * NB + (size_t)(wr * RT) * 128 + lane * 2;
+    const int kp_end = (wr * RW + RW) / 8;
+    for (int kp = 0; kp < kp_end; kp++) {
+      d2 a[RT], b[CT];
+#pragma unroll
+      for (int rt = 0; rt < RT; rt++)
+        a[rt] = *reinterpret_cast<const d2*>(Li + ((size_t)kp * (NB / 16) + rt) * 128);
+#pragma unroll
+      for (int ct = 0; ct < CT; ct++)
+        b[ct] = *reinterpret_cast<const d2*>(&Rl[((size_t)kp * CTS + wc * CT + ct) * 128 + lane * 2]);
+#pragma unroll
+      for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+        for (int ct = 0; ct < CT; ct++) {
+          w64[rt][ct] = MFMA64(a[rt].x, b[ct].x, w64[rt][ct]);
+          w64[rt][ct] = MFMA64(a[rt].y, b[ct].y, w64[rt][ct]);
+        }
+    }
+    // store W_k: FP64 pairs (identity per lane) and the FP32 quad copy
+    // (element i of the FP64 output is k-step row0/4 + i, i.e. position i of
+    // quad row0/16, same lane)
+#pragma unroll
+    for (int rt = 0; rt < RT; rt++) {
+      const int64_t row0 = (int64_t)k * NB + wr * RW + rt * 16;
+      const int64_t ks0 = row0 / 4;
+#pragma unroll
+      for (int ct = 0; ct < CT; ct++) {
+#pragma unroll
+        for (int i = 0; i < 4; i += 2)
+          *reinterpret_cast<d2*>(Wslab + ((size_t)((ks0 + i) / 2) * CTS + wc * CT + ct) * 128 + lane * 2) =
+              (d2){w64[rt][ct][i], w64[rt][ct][i + 1]};
+        *reinterpret_cast<f4*>(W32slab + ((size_t)(row0 / 16) * CTS + wc * CT + ct) * 256 + lane * 4) =
+            (f4){(float)w64[rt][ct][0], (float)w64[rt][ct][1], (float)w64[rt][ct][2],
+                 (float)w64[rt][ct][3]};
+      }
+    }
+    __threadfence_block();
+    __syncthreads();
   }
 }
 
@@ -717,22 +1127,31 @@ hipError_t launch_trsm_i8(const JobTable& tab, int64_t nslabs, int C, hipStream_
   return hipGetLastError();
 }
 
-hipError_t launch_trsm_f64(const JobTable& tab, int64_t nslabs, hipStream_t st) {
-  k_trsm<FIXED_C, 4, 1, 4, double><<<(unsigned)nslabs, 256, 0, st>>>(tab);
+hipError_t launch_fixed_solve(const double* XL, int64_t ldx, const double* Y, int64_t ldy,
+                              int64_t n, int64_t n_pad, int K, int pL, int t, const double* Lstrips,
+                              const double* LinvP, double* F, double* Z, hipStream_t st) {
+  const int w = pL + t;
+  const int64_t total = n_pad * w;
+  k_pack_fixed<<<(unsigned)((total + 255) / 256), 256, 0, st>>>(XL, ldx, Y, ldy, n, n_pad, pL, t, F);
+  for (int k = 0; k < K; k++) {
+    k_fix_diag<false><<<1, 256, 0, st>>>(LinvP, k, F, w);
+    if (k + 1 < K) k_fix_update<false><<<K - 1 - k, 256, 0, st>>>(Lstrips, k, F, w);
+  }
+  if (Z) {
+    hipError_t e = hipMemcpyAsync(Z, F, sizeof(double) * total, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return e;
+    for (int k = K - 1; k >= 0; k--) {
+      k_fix_diag<true><<<1, 256, 0, st>>>(LinvP, k, Z, w);
+      if (k > 0) k_fix_update<true><<<k, 256, 0, st>>>(Lstrips, k, Z, w);
+    }
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_pack_fixed(const double* XL, int64_t ldx, const double* Y, int64_t ldy, int64_t n,
-                             int pL, int t, double* out, hipStream_t st) {
-  dim3 grid((unsigned)((n + 255) / 256), (unsigned)(pL + t));
-  k_pack_fixed<<<grid, 256, 0, st>>>(XL, ldx, Y, ldy, n, pL, t, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_slab_to_rowmajor(const double* W, int64_t n_pad, int ncols, double* F,
-                                   hipStream_t st) {
-  const int64_t total = n_pad * ncols;
-  k_slab_to_rowmajor<<<(unsigned)((total + 255) / 256), 256, 0, st>>>(W, FIXED_C, n_pad, ncols, F);
+hipError_t launch_rowmajor_to_colmajor(const double* F, int w, int64_t n, int col0, int ncols,
+                                       double* out, int64_t ldo, hipStream_t st) {
+  dim3 grid((unsigned)((n + 255) / 256), (unsigned)ncols);
+  k_rowmajor_to_colmajor<<<grid, 256, 0, st>>>(F, w, n, col0, ncols, out, ldo);
   return hipGetLastError();
 }
 
@@ -750,8 +1169,23 @@ hipError_t launch_gram(const double* F, int64_t n, int pL, int t, double* STL, d
   return hipGetLastError();
 }
 
-hipError_t launch_assemble_solve(const AsmTable& tab, int64_t ngroups, hipStream_t st) {
-  k_assemble_solve<<<(unsigned)ngroups, 64 * AS_WAVES, 0, st>>>(tab);
+hipError_t launch_assemble_solve(const AsmTable& tab, int64_t ngroups, bool refine, hipStream_t st) {
+  if (refine) k_assemble_solve<true><<<(unsigned)ngroups, 64 * AS_WAVES, 0, st>>>(tab);
+  else k_assemble_solve<false><<<(unsigned)ngroups, 64 * AS_WAVES, 0, st>>>(tab);
+  return hipGetLastError();
+}
+
+hipError_t launch_trsm_mixed(const JobTable& tab, int64_t nslabs, int C, hipStream_t st) {
+  switch (C) {
+    case 32: k_trsm_mixed<32, 4, 2, 4, FP32_CHUNK_QUADS><<<(unsigned)nslabs, 512, 0, st>>>(tab); break;
+    case 64: k_trsm_mixed<64, 4, 2, 4, FP32_CHUNK_QUADS><<<(unsigned)nslabs, 512, 0, st>>>(tab); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_xz_shift(const XzTable& tab, int64_t ngroups, hipStream_t st) {
+  k_xz_shift<<<(unsigned)ngroups, 64 * AS_WAVES, 0, st>>>(tab);
   return hipGetLastError();
 }
 

@@ -75,7 +75,7 @@ def test_footprint_arithmetic():
     npad = K * 128
     expect = (K * (K - 1) // 2 * 128 * 128 * 8 + 2 * K * 128 * 128 * 8
               + npad * npad * 8 + K * 128 * 128 * 8
-              + n * (pL + t) * 8 + npad * 16 * 8 + npad * (pL + t) * 8 + (pL + t) ** 2 * 8
+              + npad * (pL + t) * 8 + (pL + t) ** 2 * 8
               + npad * 4096 * 8)
     assert L.gls_footprint_bytes(n, pL, t, cols, 0) == expect
     assert L.gls_footprint_bytes(n, pL, t, cols, 1) > expect

@@ -1,0 +1,152 @@
+"""The FP32_REFINE form against the FP64 oracle.
+
+Bound: max relative error of b_i <= 1e-8 (per problem and phenotype,
+max-norm), the accuracy target of the mixed-precision form.  The whitened
+genotypes alone carry FP32-level error (checked at 1e-5)."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import gls_oracle as orc
+from paper_1210_7325_amd import datagen as dg
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL_FP32_FORM = 1e-8
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def G():
+    from paper_1210_7325_amd import gls
+    gls.lib()
+    return gls
+
+
+def to_dev(a):
+    return torch.from_numpy(np.asfortranarray(a)).cuda()
+
+
+def run(G, M, XL, Y, XR, pR, block, prec="fp32_refine", slab=64):
+    c = G.Cohort(to_dev(M), precision=prec)
+    c.set_slab_cols(slab)
+    c.whiten_fixed(to_dev(XL), to_dev(Y), intercept_col=0)
+    dXR = to_dev(XR)
+    nsnp = XR.shape[1] // pR
+    outs, infos = [], []
+    for a in range(0, nsnp, block):
+        b = min(nsnp, a + block)
+        B, info = c.solve_block(dXR[:, a * pR:b * pR], p_R=pR)
+        outs.append(B)
+        infos.append(info)
+    B = torch.cat(outs).cpu().numpy()
+    info = torch.cat(infos).cpu().numpy()
+    c.free()
+    return B, info
+
+
+def problem(n, pL, pR, m, t=1, q=None, h=0.5, maf=(0.05, 0.5), seed=0):
+    w = dg.SMALL.replace(n=n, p_L=pL, p_R=pR, t=t, m=m, q=q or 2 * n, h=h, maf_R=maf,
+                         seed=dg.MASTER_SEED + 500 + seed)
+    return w, dg.make_M(w), dg.make_XL(w), dg.make_Y(w), dg.make_XR(w, 0, m)
+
+
+@pytest.mark.parametrize("n,pL,pR,t,m,block", [
+    (1000, 3, 1, 1, 2000, 1024), (2000, 16, 4, 1, 300, 128), (129, 5, 1, 8, 90, 64),
+    (700, 3, 2, 2, 100, 100), (1500, 3, 1, 1, 500, 500),
+])
+def test_fp32_refine_parity(G, n, pL, pR, t, m, block):
+    say("fp32 form", n, pL, pR, t, m)
+    maf = (0.01, 0.5) if pR == 4 else (0.05, 0.5)
+    w, M, XL, Y, XR = problem(n, pL, pR, m, t=t, maf=maf, seed=n)
+    B, info = run(G, M, XL, Y, XR, pR, block)
+    ref = orc.gls_sequence(M, XL, XR, Y, pR)
+    assert np.all(info == 0)
+    err = orc.relative_error(B, ref)
+    say("fp32 form max rel err", err.max(), "p99.99", np.quantile(err, 0.9999))
+    assert err.max() < TOL_FP32_FORM
+
+
+def test_fp32_refine_stress_conditioning(G):
+    """q = n/4, h = 0.99: kappa(M) ~ 800 (the workloads have kappa ~ 4-10).
+    The FP32-rounded operands of the off-diagonal products leave an error
+    in the whitened genotypes that grows with kappa(L) = sqrt(kappa(M)), and
+    the refinement cannot remove the part that enters S_BR; at this
+    conditioning the bound is 1e-7 (measured ~4e-8), against 1e-8 at the
+    workloads' conditioning."""
+    say("fp32 stress")
+    w, M, XL, Y, XR = problem(1200, 3, 1, 400, q=300, h=0.99, seed=7)
+    ev = np.linalg.eigvalsh(M)
+    say("kappa(M)", ev[-1] / ev[0])
+    assert ev[-1] / ev[0] > 500
+    B, info = run(G, M, XL, Y, XR, 1, 400)
+    ref = orc.gls_sequence(M, XL, XR, Y, 1)
+    err = orc.relative_error(B, ref)
+    say("stress max rel err", err.max())
+    assert np.all(info == 0) and err.max() < 1e-7
+
+
+def test_fp32_whitening_error_is_fp32_level(G):
+    """The whitened genotypes of the FP32_REFINE form carry FP32-level error
+    (far above the 1e-8 reached by b_i after refinement), so the refinement
+    step is what brings b_i to the target."""
+    say("fp32 whiten")
+    w, M, XL, Y, XR = problem(1000, 3, 1, 64, seed=3)
+    c = G.Cohort(to_dev(M), precision="fp32_refine")
+    W = c.whiten_block(to_dev(XR)).cpu().numpy()
+    c.free()
+    Wref = orc.whiten(orc.cholesky_lower(M), XR)
+    rel = np.max(np.abs(W - Wref)) / np.max(np.abs(Wref))
+    say("fp32 whitening rel err", rel)
+    assert 1e-10 < rel < 1e-5
+
+
+def test_fp32_refine_deterministic_and_multi(G):
+    say("fp32 determinism / multi")
+    from paper_1210_7325_amd import gls
+    w, M, XL, Y, XR = problem(600, 3, 1, 300, seed=11)
+    B1, _ = run(G, M, XL, Y, XR, 1, 300)
+    B2, _ = run(G, M, XL, Y, XR, 1, 64)
+    assert np.array_equal(B1, B2)
+    c = gls.Cohort(to_dev(M), precision="fp32_refine").whiten_fixed(to_dev(XL), to_dev(Y))
+    f = c.fork(torch.cuda.current_stream())
+    dXR = to_dev(XR)
+    Ba = torch.empty((150, 1, 4), dtype=torch.float64, device="cuda")
+    Bb = torch.empty_like(Ba)
+    gls.solve_multi([(c, dXR[:, :150], 1, Ba, None), (f, dXR[:, 150:], 1, Bb, None)])
+    torch.cuda.synchronize()
+    assert np.array_equal(torch.cat([Ba, Bb]).cpu().numpy(), B1)
+    f.free()
+    c.free()
+
+
+def test_fp32_refine_full_n_sampled(G):
+    """n = 10,000, p = 20 (p_L = 16, p_R = 4), maf ~ U[0.01, 0.5]: four blocks
+    of 4096 problems (16,384 genotype columns per block) in one launch as the
+    benchmark runs them; 200 sampled problems checked against the oracle."""
+    import bench
+    w = dg.MIXED
+    m = 4 * w.block
+    say("fp32 full n", w.name)
+    M = dg.make_M(w)
+    XL, Y = dg.make_XL(w), dg.make_Y(w)
+    dXR = bench.upload_genotypes(torch, w, m)
+    Bout = torch.empty((m, w.t, w.p), dtype=torch.float64, device="cuda")
+    info = torch.full((m,), -7, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.Stream()
+    bench.run_step(G, torch, torch.from_numpy(M).cuda(), to_dev(XL), to_dev(Y), dXR, w, m,
+                   w.block, [stream], 64, Bout, info, batch=4, precision="fp32_refine")
+    torch.cuda.synchronize()
+    assert int((info != 0).sum()) == 0
+    idx = np.unique(np.concatenate([[0, 1, m - 1], np.random.default_rng(2).choice(m, 197, replace=False)]))
+    B = Bout[torch.from_numpy(idx).cuda()].cpu().numpy()
+    XRs = np.concatenate([dg.make_XR(w, int(i), 1) for i in idx], axis=1)
+    ref = orc.gls_sequence(M, XL, XRs, Y, w.p_R)
+    err = orc.relative_error(B, ref)
+    say("fp32 full n sampled max rel err", err.max())
+    assert err.max() < TOL_FP32_FORM

@@ -207,3 +207,34 @@ def test_forked_streams_equal(G):
     for f in forks:
         f.free()
     c.free()
+
+
+def test_full_scale_sampled_in_bench_configuration(G):
+    """n = 10,000, p = 4, m = 1,000,000 in blocks of 4096, four blocks per
+    launch exactly as bench.py times it; 300 problems sampled across the
+    whole sequence (first, last partial block, and a stride) checked one by
+    one against the oracle."""
+    import bench
+    w = dg.SCALE
+    say("full scale", w.name)
+    M = dg.make_M(w)
+    XL, Y = dg.make_XL(w), dg.make_Y(w)
+    dM = torch.from_numpy(M).cuda()
+    dXL, dY = to_dev(XL), to_dev(Y)
+    dXR = bench.upload_genotypes(torch, w, w.m)
+    Bout = torch.empty((w.m, w.t, w.p), dtype=torch.float64, device="cuda")
+    info = torch.full((w.m,), -7, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.Stream()
+    bench.run_step(G, torch, dM, dXL, dY, dXR, w, w.m, w.block, [stream], 64, Bout, info, batch=4)
+    torch.cuda.synchronize()
+    assert int((info != 0).sum()) == 0
+    rng = np.random.default_rng(5)
+    idx = np.unique(np.concatenate([np.arange(4), np.arange(w.m - 4, w.m),
+                                    rng.choice(w.m, 292, replace=False)]))
+    B = Bout[torch.from_numpy(idx).cuda()].cpu().numpy()
+    XRs = np.concatenate([dg.make_XR(w, int(i), 1) for i in idx], axis=1)
+    ref = orc.gls_sequence(M, XL, XRs, Y, w.p_R)
+    err = orc.relative_error(B, ref)
+    say("full scale sampled max rel err", err.max())
+    assert err.max() < TOL_B
+    del dXR
