@@ -3,14 +3,18 @@
 One step = one whole pass of the in-core algorithm (Sec. 2, Alg. 5) over
 the throughput workload: factor M (n = 10,000), whiten X_L and y, then solve
 m = 1,000,000 single-SNP problems (p = 4) in blocks of 4096 SNPs, every
-input resident in HBM before the clock starts.  Blocks are distributed
-`--batch` at a time to one launch (gls_solve_multi over handles that share
-the factor through gls_fork, each with its own workspace), so a single
-launch fills the chip.
+input resident in HBM before the clock starts.  Blocks are handed `--batch`
+at a time to one launch (gls_solve_multi over handles that share the factor
+through gls_fork, each with its own workspace), so a single launch fills the
+chip.
 
-Prints ONE JSON line (see the fields below); progress goes to stderr.
+The same steps are then timed in the FP32_REFINE form, and both forms are
+checked against the CPU oracle on a sample of problems.  `--workload mixed`
+runs the p = 20 (p_L = 16, p_R = 4) mixed-precision workload instead.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W]
+Prints ONE JSON line; progress goes to stderr.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload scale|mixed]
 """
 from __future__ import annotations
 
@@ -34,6 +38,7 @@ PEAK_HBM_GBS = 8000.0
 # the paper's in-core/out-of-core time for n=10^4, p=4, m=10^6 on 12 Xeon
 # cores (Table 3): 816 s, i.e. 1,225 solves/s
 PAPER_BI_PER_S = 1_000_000 / 816.0
+WORKLOADS = {"scale": dg.SCALE, "mixed": dg.MIXED}
 
 
 def log(*a):
@@ -45,11 +50,17 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="scale")
     ap.add_argument("--m", type=int, default=None, help="problems per step (default: workload m)")
     ap.add_argument("--block", type=int, default=None, help="SNPs per solve call (default 4096)")
     ap.add_argument("--streams", type=int, default=1)
-    ap.add_argument("--batch", type=int, default=4, help="blocks whitened per launch")
+    ap.add_argument("--batch", type=int, default=None,
+                    help="blocks whitened per launch (default: 4 / p_R)")
     ap.add_argument("--slab-cols", type=int, default=64)
+    ap.add_argument("--forms", default="fp64,fp32_refine",
+                    help="precisions to time, the first is the headline")
+    ap.add_argument("--parity-sample", type=int, default=1000,
+                    help="problems checked against the oracle per form (0 skips)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="budget of the oracle's CPU sample (0 skips it)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -57,11 +68,13 @@ def parse():
     return ap.parse_args()
 
 
-def measured_traffic(batch, slab_cols):
+def measured_traffic(batch, slab_cols, precision):
     """HBM bytes per launch of the FP64 triangular-solve kernel from the
     committed rocprofv3 counter summary, or None if the kernel source has
     changed since the counters were taken (or the launch shape differs)."""
     import hashlib
+    if precision != "fp64":
+        return None
     path = os.path.join(ROOT, "profiles", "trsm_fp64_n10000_traffic.md")
     src = os.path.join(ROOT, "paper_1210_7325_amd", "csrc", "gls_kernels.hip")
     try:
@@ -92,15 +105,21 @@ def upload_genotypes(torch, w, m):
     generated on the host in chunks and copied through pinned memory."""
     ncols = m * w.p_R
     dev = torch.empty((ncols, w.n), dtype=torch.int8, device="cuda")
-    chunk = max(1, (256 << 20) // w.n)
+    chunk = max(w.p_R, (256 << 20) // w.n // w.p_R * w.p_R)
     pinned = [torch.empty((chunk, w.n), dtype=torch.int8).pin_memory() for _ in range(2)]
+    done = [None, None]
     t0 = time.time()
     for i, a in enumerate(range(0, m, chunk // w.p_R)):
         b = min(m, a + chunk // w.p_R)
-        buf = pinned[i % 2]
-        torch.cuda.current_stream().synchronize() if i >= 2 else None
+        k = i % 2
+        if done[k] is not None:
+            done[k].synchronize()
+        buf = pinned[k]
         dg.make_XR(w, a, b - a, out=buf.numpy())
         dev[a * w.p_R:b * w.p_R].copy_(buf[:(b - a) * w.p_R], non_blocking=True)
+        ev = torch.cuda.Event()
+        ev.record()
+        done[k] = ev
     torch.cuda.synchronize()
     log(f"genotypes: {ncols} columns x {w.n} in {time.time() - t0:.1f}s")
     return dev.t()
@@ -144,7 +163,60 @@ def run_step(gls, torch, dM, dXL, dY, dXR, w, m, block, streams, slab_cols, Bout
     return times
 
 
-def cpu_baseline(w, M, XL, Y, budget_s):
+def time_form(gls, torch, args, w, m, block, batch, dM, dXL, dY, dXR, Bout, info, precision):
+    streams = [torch.cuda.Stream() for _ in range(args.streams)]
+    for i in range(args.warmup):
+        run_step(gls, torch, dM, dXL, dY, dXR, w, m, block, streams, args.slab_cols, Bout, info,
+                 batch=batch, precision=precision)
+        log(f"[{precision}] warmup step {i} done")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kt = []
+    for i in range(args.steps):
+        kt.append(run_step(gls, torch, dM, dXL, dY, dXR, w, m, block, streams, args.slab_cols,
+                           Bout, info, timing=True, batch=batch, precision=precision))
+        log(f"[{precision}] step {i} done")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    trsm_ms = sum(t[0][0] for step in kt for t in step)
+    trsm_n = sum(t[0][1] for step in kt for t in step)
+    asm_ms = sum(t[1][0] for step in kt for t in step)
+    asm_n = sum(t[1][1] for step in kt for t in step)
+    # algorithmic work of the triangular solve: n^2 flops per right-hand side
+    flops_per_launch = float(w.n) ** 2 * (m * w.p_R) / (trsm_n / args.steps)
+    achieved = flops_per_launch / (trsm_ms / trsm_n * 1e-3) / 1e12
+    peak = PEAK_FP64_TFLOPS if precision == "fp64" else PEAK_FP32_TFLOPS
+    step_tflops = float(w.n) ** 2 * m * w.p_R * args.steps / dt / 1e12
+    r = {
+        "value": m * args.steps / dt, "ms_per_step": dt / args.steps * 1e3,
+        "trsm_launches": trsm_n, "trsm_avg_ms": trsm_ms / trsm_n,
+        "flops_per_launch": flops_per_launch, "trsm_tflops": achieved, "peak": peak,
+        "step_tflops": step_tflops, "assemble_avg_ms": asm_ms / max(asm_n, 1),
+        "rank_deficient": int((info != 0).sum()),
+    }
+    log(f"[{precision}] {r['value']:.0f} b_i/s, {r['ms_per_step']:.1f} ms/step, TRSM "
+        f"{achieved:.1f} TFLOP/s ({achieved / peak * 100:.1f}% of {peak}), step {step_tflops:.1f}")
+    return r
+
+
+def parity_sample(w, m, M, XL, Y, lu, outs, sample):
+    """Max / p99.99 relative error of each form against the oracle on a
+    sample of problems spread over the whole sequence."""
+    from oracle import gls_oracle as orc
+    rng = np.random.default_rng(12107325)
+    idx = np.unique(np.concatenate([[0, m - 1], rng.choice(m, min(sample, m) - 2, replace=False)]))
+    XRs = np.concatenate([dg.make_XR(w, int(i), 1) for i in idx], axis=1)
+    ref = orc.gls_sequence(M, XL, XRs, Y, w.p_R, lu=lu)
+    res = {}
+    for name, B in outs.items():
+        err = orc.relative_error(B[idx], ref)
+        res[name] = {"max_rel_err": float(err.max()), "p9999_rel_err": float(np.quantile(err, 0.9999)),
+                     "sample": int(len(idx))}
+        log(f"[{name}] parity on {len(idx)} problems: max rel err {err.max():.3e}")
+    return res
+
+
+def cpu_baseline(w, M, XL, Y, budget_s, lu=None, t_factor=None):
     """The oracle, as it stands, on the host cores: LU factorization of M plus
     per-problem solves on a bounded sample, extrapolated linearly in m."""
     from oracle import gls_oracle as orc
@@ -154,9 +226,10 @@ def cpu_baseline(w, M, XL, Y, budget_s):
         cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [os.cpu_count()])
     except Exception:  # pragma: no cover
         cores = os.cpu_count()
-    t0 = time.time()
-    lu = sla.lu_factor(M)
-    t_factor = time.time() - t0
+    if lu is None:
+        t0 = time.time()
+        lu = sla.lu_factor(M)
+        t_factor = time.time() - t0
     pilot = 64
     XR = dg.make_XR(w, 0, pilot)
     t0 = time.time()
@@ -185,13 +258,16 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         log("bench.py: only --gpus 1 is supported (one GPU per box)")
         sys.exit(2)
+    import scipy.linalg as sla
     import torch
     from paper_1210_7325_amd import gls
 
     gls.lib()
-    w = dg.SCALE
+    w = WORKLOADS[args.workload]
     m = args.m or w.m
     block = args.block or w.block
+    batch = args.batch or max(1, 4 // w.p_R)
+    forms = args.forms.split(",")
     torch.cuda.set_device(0)
 
     t0 = time.time()
@@ -202,67 +278,67 @@ def main():
     dXL = torch.from_numpy(np.asfortranarray(XL)).cuda()
     dY = torch.from_numpy(np.asfortranarray(Y)).cuda()
     dXR = upload_genotypes(torch, w, m)
-    Bout = torch.empty((m, w.t, w.p), dtype=torch.float64, device="cuda")
     info = torch.empty((m,), dtype=torch.int32, device="cuda")
-    streams = [torch.cuda.Stream() for _ in range(args.streams)]
 
-    for i in range(args.warmup):
-        run_step(gls, torch, dM, dXL, dY, dXR, w, m, block, streams, args.slab_cols, Bout, info,
-                 batch=args.batch)
-        log(f"warmup step {i} done")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    kt = []
-    for i in range(args.steps):
-        kt.append(run_step(gls, torch, dM, dXL, dY, dXR, w, m, block, streams, args.slab_cols,
-                           Bout, info, timing=True, batch=args.batch))
-        log(f"step {i} done")
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ms_step = dt / args.steps * 1e3
-    value = m * args.steps / dt
-    bad = int((info != 0).sum())
+    results, outs = {}, {}
+    for prec in forms:
+        Bout = torch.empty((m, w.t, w.p), dtype=torch.float64, device="cuda")
+        results[prec] = time_form(gls, torch, args, w, m, block, batch, dM, dXL, dY, dXR, Bout,
+                                  info, prec)
+        outs[prec] = Bout.cpu().numpy()
+        del Bout
+    del dXR
 
-    trsm_ms = sum(t[0][0] for step in kt for t in step)
-    trsm_n = sum(t[0][1] for step in kt for t in step)
-    asm_ms = sum(t[1][0] for step in kt for t in step)
-    asm_n = sum(t[1][1] for step in kt for t in step)
-    # algorithmic work of the triangular solve: n^2 flops per right-hand side
-    flops_per_launch = float(w.n) ** 2 * (m * w.p_R) / (trsm_n / args.steps)
-    avg_trsm_s = trsm_ms / trsm_n * 1e-3
-    achieved = flops_per_launch / avg_trsm_s / 1e12
-    # all blocks of a step in flight on `streams` streams: the chip-wide rate
-    chip_tflops = float(w.n) ** 2 * m * w.p_R * args.steps / dt / 1e12
-    roofline = {
-        "bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
-        "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
-        "traffic": measured_traffic(args.batch, args.slab_cols),
-        "kernel": "k_trsm<int8> (FP64 MFMA)", "launches": trsm_n,
-        "avg_launch_ms": round(trsm_ms / trsm_n, 4),
-        "flops_per_launch": flops_per_launch, "concurrent_streams": args.streams,
-        "blocks_per_launch": args.batch,
-        "step_tflops": round(chip_tflops, 3), "step_frac": round(chip_tflops / PEAK_FP64_TFLOPS, 4),
-        "assemble_avg_launch_ms": round(asm_ms / max(asm_n, 1), 4),
-    }
-    log(f"GPU: {value:.0f} b_i/s, {ms_step:.1f} ms/step, step {chip_tflops:.1f} TFLOP/s, "
-        f"trsm launch avg {trsm_ms / trsm_n:.3f} ms, rank-deficient {bad}")
-
+    lu, t_factor = None, None
+    parity = {}
+    if args.parity_sample > 0 or args.cpu_seconds > 0:
+        t0 = time.time()
+        lu = sla.lu_factor(M)
+        t_factor = time.time() - t0
+    if args.parity_sample > 0:
+        parity = parity_sample(w, m, M, XL, Y, lu, outs, args.parity_sample)
     cpu = None
     if args.cpu_seconds > 0:
         log("cpu baseline (oracle) ...")
-        cpu = cpu_baseline(w, M, XL, Y, args.cpu_seconds)
+        cpu = cpu_baseline(w, M, XL, Y, args.cpu_seconds, lu=lu, t_factor=t_factor)
         log(f"cpu: {cpu['value']:.1f} b_i/s ({cpu['sample']})")
 
+    head = results[forms[0]]
+    roofline = {
+        "bound": "mfma", "achieved": round(head["trsm_tflops"], 3), "peak": head["peak"],
+        "unit": "TFLOP/s", "frac": round(head["trsm_tflops"] / head["peak"], 4),
+        "traffic": measured_traffic(batch, args.slab_cols, forms[0]),
+        "kernel": "k_trsm (blocked lower solve, " + ("FP64 MFMA)" if forms[0] == "fp64" else
+                                                      "FP32 MFMA products + FP64 diagonal)"),
+        "launches": head["trsm_launches"], "avg_launch_ms": round(head["trsm_avg_ms"], 4),
+        "flops_per_launch": head["flops_per_launch"], "blocks_per_launch": batch,
+        "step_tflops": round(head["step_tflops"], 3),
+        "step_frac": round(head["step_tflops"] / head["peak"], 4),
+        "assemble_avg_launch_ms": round(head["assemble_avg_ms"], 4),
+    }
+    form_out = {}
+    for prec in forms[1:]:
+        r = results[prec]
+        form_out[prec] = {
+            "value": round(r["value"], 1), "unit": "b_i/s", "ms_per_step": round(r["ms_per_step"], 2),
+            "speedup_vs_" + forms[0]: round(r["value"] / head["value"], 3),
+            "trsm_tflops": round(r["trsm_tflops"], 3), "trsm_peak": r["peak"],
+            "trsm_frac": round(r["trsm_tflops"] / r["peak"], 4),
+            "trsm_avg_launch_ms": round(r["trsm_avg_ms"], 4),
+            **parity.get(prec, {}),
+        }
     out = {
-        "metric": METRIC, "value": round(value, 1), "unit": "b_i/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 2),
+        "metric": METRIC, "value": round(head["value"], 1), "unit": "b_i/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(head["ms_per_step"], 2),
         "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": round(value / PAPER_BI_PER_S, 2), "dtype": "f64", "data": "synthetic",
+        "vs_baseline": round(head["value"] / PAPER_BI_PER_S, 2) if w is dg.SCALE else None,
+        "dtype": "f64" if forms[0] == "fp64" else "f32+f64", "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "p": w.p, "p_L": w.p_L, "p_R": w.p_R, "t": w.t,
-                   "m": m, "block": block, "blocks_per_launch": args.batch, "streams": args.streams,
+                   "m": m, "block": block, "blocks_per_launch": batch, "streams": args.streams,
                    "slab_cols": args.slab_cols,
                    "M": f"h*ZZ^T/q+(1-h)I+1e-3I, q={w.q}, h={w.h}", "parallelism": "1 GPU"},
         "roofline": roofline, "cpu_baseline": cpu,
+        "parity": parity.get(forms[0]), "forms": form_out,
         "baseline_note": "vs_baseline divides by the paper's 12-core CPU rate for the same "
                          "workload (816 s for m=10^6, Table 3): context, other hardware",
     }
