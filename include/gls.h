@@ -172,6 +172,45 @@ int gls_set_slab_cols(gls_handle h, int cols);
 int gls_set_kernel_timing(gls_handle h, int enable);
 int gls_kernel_time(gls_handle h, int kind, double* ms, int64_t* launches);
 
+/* ---- streamed genotypes (out-of-core, Sec. 4, Alg. 8) -------------------
+ * Solves problems [snp_begin, snp_end) of h's cohort in blocks of `block`
+ * problems whose genotypes live on the host (or on disk) and are produced
+ * on demand by `fill`, with double buffering: while block j is solved on
+ * h's stream, block j+1 is filled into pinned host memory and copied to the
+ * device on a second stream, and the b of block j-1 is copied back on a
+ * third stream and handed to `sink` (Alg. 8: async read of the next block,
+ * wait for the current one, compute, async write, wait for the previous).
+ * fill(fill_ctx, snp0, nsnp, buf, ld) writes the n x (nsnp*p_R) int8
+ *   genotypes of problems snp0.. into pinned host memory buf (column j at
+ *   buf + j*ld, ld = n); it returns 0, or nonzero to abort the stream.
+ * sink(sink_ctx, snp0, nsnp, b, info) receives host pointers to the
+ *   (nsnp, t, p) results and nsnp info codes of those problems, valid during
+ *   the call; sinks are called in block order; nonzero aborts.
+ * fill and sink work per block; the device solves superblocks of several
+ * consecutive blocks (at least one slab of columns per compute unit per
+ * launch), which changes no result bit.
+ * snp_begin may be any block boundary of an earlier run: a stream that was
+ * aborted resumes after the last block its sink accepted and yields the
+ * same bits.  SYNCHRONOUS.  The library allocates (and frees) two pinned
+ * input and output buffers, two device input and output buffers and two
+ * streams.  stats (nullable) receives wall, fill, sink and wait times. */
+typedef int (*gls_fill_fn)(void* fill_ctx, int64_t snp0, int64_t nsnp, int8_t* buf, int64_t ld);
+typedef int (*gls_sink_fn)(void* sink_ctx, int64_t snp0, int64_t nsnp, const double* b,
+                           const int32_t* info);
+typedef struct {
+  double wall_ms;       /* whole call                                        */
+  double fill_ms;       /* time inside fill                                  */
+  double sink_ms;       /* time inside sink                                  */
+  double wait_ms;       /* host time blocked on device work (exposed compute) */
+  int64_t blocks;
+  int64_t bytes_h2d;
+  int64_t bytes_d2h;
+} gls_stream_stats;
+
+int gls_solve_stream(gls_handle h, int64_t snp_begin, int64_t snp_end, int64_t block,
+                     int64_t p_R, gls_fill_fn fill, void* fill_ctx, gls_sink_fn sink,
+                     void* sink_ctx, gls_stream_stats* stats);
+
 /* ---- several cohorts in one launch (serving) ----------------------------
  * One work item per block of problems of one handle.  All items are
  * whitened by one launch of the triangular-solve kernel and assembled and

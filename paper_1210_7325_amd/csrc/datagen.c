@@ -84,3 +84,18 @@ void gen_uniforms(uint64_t seed, uint64_t stream, int64_t nidx, int64_t col0,
     for (int64_t i = 0; i < nidx; i++) out[j * ld + i] = unit_draw(ck, (uint64_t)i);
   }
 }
+
+/* Fill callback for a streamed solve: the genotypes of problems
+ * snp0 .. snp0+nsnp-1 (p_R columns each) into buf (column j at buf + j*ld). */
+typedef struct {
+  uint64_t seed, stream_maf, stream_g;
+  double lo, hi;
+  int64_t n, p_R;
+} gen_fill_ctx;
+
+int gen_fill_genotypes(void* ctx, int64_t snp0, int64_t nsnp, int8_t* buf, int64_t ld) {
+  const gen_fill_ctx* c = (const gen_fill_ctx*)ctx;
+  gen_genotypes(c->seed, c->stream_maf, c->stream_g, c->lo, c->hi, c->n, snp0 * c->p_R,
+                nsnp * c->p_R, buf, ld);
+  return 0;
+}

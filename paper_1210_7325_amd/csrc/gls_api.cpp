@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -557,6 +558,165 @@ int gls_kernel_time(gls_handle h, int kind, double* ms, int64_t* launches) {
   }
   *ms = sum;
   *launches = cnt;
+  return GLS_OK;
+}
+
+int gls_solve_stream(gls_handle h, int64_t snp_begin, int64_t snp_end, int64_t block, int64_t p_R,
+                     gls_fill_fn fill, void* fill_ctx, gls_sink_fn sink, void* sink_ctx,
+                     gls_stream_stats* stats) {
+  using clk = std::chrono::steady_clock;
+  auto ms_since = [](clk::time_point t0) {
+    return std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+  };
+  const auto t_start = clk::now();
+  if (!h) return -1;
+  if (snp_begin < 0) return -2;
+  if (snp_end < snp_begin) return -3;
+  if (block < 1) return -4;
+  if (!fill) return -6;
+  if (!sink) return -8;
+  if (!h->c->fixed) return GLS_E_STATE;
+  const int64_t n = h->c->n, t = h->c->t, p = h->c->pL + p_R;
+  if (p_R < 1 || p_R > 16 || p > MAXP || n <= p) return -5;
+  gls_stream_stats st{};
+  if (snp_end == snp_begin) {
+    if (stats) *stats = st;
+    return GLS_OK;
+  }
+  // I/O happens per block of `block` problems; the device solves
+  // superblocks of `group` consecutive blocks so that one launch has at
+  // least one slab per CU (results do not depend on the grouping)
+  const int64_t target_cols = 256 * (int64_t)h->C;
+  const int64_t group = std::max<int64_t>(1, (target_cols + block * p_R - 1) / (block * p_R));
+  const int64_t sbk = group * block;  // problems per superblock
+  const int64_t cols = sbk * p_R;
+  int rc = ensure_workspace(h, cols);
+  if (rc) return rc;
+
+  int8_t* hin[2] = {nullptr, nullptr};
+  int8_t* din[2] = {nullptr, nullptr};
+  double* hB[2] = {nullptr, nullptr};
+  double* dB[2] = {nullptr, nullptr};
+  int32_t* hinfo[2] = {nullptr, nullptr};
+  int32_t* dinfo[2] = {nullptr, nullptr};
+  hipStream_t s_in = nullptr, s_out = nullptr;
+  hipEvent_t ev_in[2] = {nullptr, nullptr}, ev_comp[2] = {nullptr, nullptr},
+             ev_out[2] = {nullptr, nullptr};
+  const size_t in_bytes = (size_t)n * cols, out_n = (size_t)sbk * t * p;
+  auto cleanup = [&]() {
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    if (s_in) (void)hipStreamSynchronize(s_in);
+    if (s_out) (void)hipStreamSynchronize(s_out);
+    for (int i = 0; i < 2; i++) {
+      if (hin[i]) (void)hipHostFree(hin[i]);
+      if (hB[i]) (void)hipHostFree(hB[i]);
+      if (hinfo[i]) (void)hipHostFree(hinfo[i]);
+      dfree(din[i]);
+      dfree(dB[i]);
+      dfree(dinfo[i]);
+      if (ev_in[i]) (void)hipEventDestroy(ev_in[i]);
+      if (ev_comp[i]) (void)hipEventDestroy(ev_comp[i]);
+      if (ev_out[i]) (void)hipEventDestroy(ev_out[i]);
+    }
+    if (s_in) (void)hipStreamDestroy(s_in);
+    if (s_out) (void)hipStreamDestroy(s_out);
+  };
+#define STREAM_CHK(x)               \
+  do {                              \
+    hipError_t e_ = (x);            \
+    if (e_ != hipSuccess) {         \
+      cleanup();                    \
+      return hip_code(e_);          \
+    }                               \
+  } while (0)
+  for (int i = 0; i < 2; i++) {
+    STREAM_CHK(hipHostMalloc(reinterpret_cast<void**>(&hin[i]), in_bytes, hipHostMallocDefault));
+    STREAM_CHK(hipHostMalloc(reinterpret_cast<void**>(&hB[i]), out_n * sizeof(double), hipHostMallocDefault));
+    STREAM_CHK(hipHostMalloc(reinterpret_cast<void**>(&hinfo[i]), sbk * sizeof(int32_t), hipHostMallocDefault));
+    STREAM_CHK(hipMalloc(reinterpret_cast<void**>(&din[i]), in_bytes));
+    STREAM_CHK(hipMalloc(reinterpret_cast<void**>(&dB[i]), out_n * sizeof(double)));
+    STREAM_CHK(hipMalloc(reinterpret_cast<void**>(&dinfo[i]), sbk * sizeof(int32_t)));
+    STREAM_CHK(hipEventCreateWithFlags(&ev_in[i], hipEventDisableTiming));
+    STREAM_CHK(hipEventCreateWithFlags(&ev_comp[i], hipEventDisableTiming));
+    STREAM_CHK(hipEventCreateWithFlags(&ev_out[i], hipEventDisableTiming));
+  }
+  STREAM_CHK(hipStreamCreateWithFlags(&s_in, hipStreamNonBlocking));
+  STREAM_CHK(hipStreamCreateWithFlags(&s_out, hipStreamNonBlocking));
+
+  const int64_t nsb = (snp_end - snp_begin + sbk - 1) / sbk;
+  auto sb_snp0 = [&](int64_t j) { return snp_begin + j * sbk; };
+  auto sb_len = [&](int64_t j) { return std::min<int64_t>(sbk, snp_end - sb_snp0(j)); };
+  auto drain = [&](int64_t j) -> int {
+    const int sj = (int)(j % 2);
+    const auto tw = clk::now();
+    hipError_t e = hipEventSynchronize(ev_out[sj]);
+    st.wait_ms += ms_since(tw);
+    if (e != hipSuccess) return hip_code(e);
+    const int64_t len = sb_len(j);
+    for (int64_t o = 0; o < len; o += block) {
+      const int64_t nb = std::min<int64_t>(block, len - o);
+      const auto ts = clk::now();
+      const int r = sink(sink_ctx, sb_snp0(j) + o, nb, hB[sj] + (size_t)o * t * p, hinfo[sj] + o);
+      st.sink_ms += ms_since(ts);
+      if (r) return GLS_E_STATE;
+      st.blocks++;
+    }
+    st.bytes_d2h += (int64_t)(len * (t * p * sizeof(double) + sizeof(int32_t)));
+    return GLS_OK;
+  };
+  for (int64_t j = 0; j < nsb; j++) {
+    const int sj = (int)(j % 2);
+    const int64_t len = sb_len(j);
+    // pinned input sj is free once the copy of superblock j-2 has completed
+    if (j >= 2) {
+      const auto tw = clk::now();
+      STREAM_CHK(hipEventSynchronize(ev_in[sj]));
+      st.wait_ms += ms_since(tw);
+    }
+    for (int64_t o = 0; o < len; o += block) {
+      const int64_t nb = std::min<int64_t>(block, len - o);
+      const auto tf = clk::now();
+      const int fr = fill(fill_ctx, sb_snp0(j) + o, nb, hin[sj] + (size_t)o * p_R * n, n);
+      st.fill_ms += ms_since(tf);
+      if (fr) {
+        cleanup();
+        return GLS_E_STATE;
+      }
+    }
+    // device input sj is free once the solve of superblock j-2 has finished
+    if (j >= 2) STREAM_CHK(hipStreamWaitEvent(s_in, ev_comp[sj], 0));
+    STREAM_CHK(hipMemcpyAsync(din[sj], hin[sj], (size_t)n * len * p_R, hipMemcpyHostToDevice, s_in));
+    STREAM_CHK(hipEventRecord(ev_in[sj], s_in));
+    st.bytes_h2d += n * len * p_R;
+    // solve on the handle's stream after the copy; device output sj is
+    // free once the copy-back of superblock j-2 has finished
+    STREAM_CHK(hipStreamWaitEvent(h->stream, ev_in[sj], 0));
+    if (j >= 2) STREAM_CHK(hipStreamWaitEvent(h->stream, ev_out[sj], 0));
+    gls_work w{h, len, p_R, din[sj], n, dB[sj], p, dinfo[sj]};
+    rc = launch_items(&w, 1, h->stream, h);
+    if (rc) {
+      cleanup();
+      return rc;
+    }
+    STREAM_CHK(hipEventRecord(ev_comp[sj], h->stream));
+    STREAM_CHK(hipStreamWaitEvent(s_out, ev_comp[sj], 0));
+    STREAM_CHK(hipMemcpyAsync(hB[sj], dB[sj], (size_t)len * t * p * sizeof(double), hipMemcpyDeviceToHost, s_out));
+    STREAM_CHK(hipMemcpyAsync(hinfo[sj], dinfo[sj], (size_t)len * sizeof(int32_t), hipMemcpyDeviceToHost, s_out));
+    STREAM_CHK(hipEventRecord(ev_out[sj], s_out));
+    // hand over the previous superblock while this one computes
+    if (j >= 1 && (rc = drain(j - 1))) {
+      cleanup();
+      return rc;
+    }
+  }
+  if ((rc = drain(nsb - 1))) {
+    cleanup();
+    return rc;
+  }
+#undef STREAM_CHK
+  cleanup();
+  st.wall_ms = ms_since(t_start);
+  if (stats) *stats = st;
   return GLS_OK;
 }
 

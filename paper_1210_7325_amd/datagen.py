@@ -204,9 +204,11 @@ def make_Z(w: Workload) -> np.ndarray:
 
 
 def make_phi(w: Workload) -> np.ndarray:
-    """Phi = Z Z^T / q, made exactly symmetric (lower triangle mirrored)."""
-    Z = make_Z(w)
-    A = (Z @ Z.T) / float(w.q)
+    """Phi = Z Z^T / q (symmetric rank-q update of the lower triangle, then
+    mirrored so that the matrix is exactly symmetric)."""
+    from scipy.linalg.blas import dsyrk
+    Z = np.asfortranarray(make_Z(w))
+    A = dsyrk(1.0 / float(w.q), Z, lower=1)
     return _mirror_lower(A)
 
 

@@ -30,7 +30,8 @@ GLS_OK, GLS_E_NOT_SPD, GLS_E_STATE, GLS_E_OOM, GLS_E_HIP, GLS_E_UNSUPPORTED = 0,
 EXPORTS = ("gls_factor", "gls_whiten_fixed", "gls_solve_block", "gls_reserve", "gls_free",
            "gls_fork", "gls_set_stream", "gls_footprint_bytes", "gls_last_info",
            "gls_strerror", "gls_copy_factor", "gls_copy_fixed", "gls_whiten_block",
-           "gls_solve_multi", "gls_set_slab_cols", "gls_set_kernel_timing", "gls_kernel_time")
+           "gls_solve_multi", "gls_set_slab_cols", "gls_set_kernel_timing", "gls_kernel_time",
+           "gls_solve_stream")
 
 _i64, _p, _int = ctypes.c_int64, ctypes.c_void_p, ctypes.c_int
 
@@ -38,6 +39,17 @@ _i64, _p, _int = ctypes.c_int64, ctypes.c_void_p, ctypes.c_int
 class gls_work(ctypes.Structure):
     _fields_ = [("h", _p), ("nsnp", _i64), ("p_R", _i64), ("X_R", _p), ("ldxr", _i64),
                 ("B", _p), ("ldb", _i64), ("info", _p)]
+
+
+class gls_stream_stats(ctypes.Structure):
+    _fields_ = [("wall_ms", ctypes.c_double), ("fill_ms", ctypes.c_double),
+                ("sink_ms", ctypes.c_double), ("wait_ms", ctypes.c_double),
+                ("blocks", _i64), ("bytes_h2d", _i64), ("bytes_d2h", _i64)]
+
+
+FILL_FN = ctypes.CFUNCTYPE(_int, _p, _i64, _i64, _p, _i64)
+SINK_FN = ctypes.CFUNCTYPE(_int, _p, _i64, _i64, ctypes.POINTER(ctypes.c_double),
+                           ctypes.POINTER(ctypes.c_int32))
 
 
 class GLSError(RuntimeError):
@@ -74,6 +86,8 @@ def lib() -> ctypes.CDLL:
             "gls_set_kernel_timing": (_int, [_p, _int]),
             "gls_kernel_time": (_int, [_p, _int, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(_i64)]),
+            "gls_solve_stream": (_int, [_p, _i64, _i64, _i64, _i64, _p, _p, _p, _p,
+                                        ctypes.POINTER(gls_stream_stats)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -171,6 +185,17 @@ def gls_kernel_time(h, kind) -> Tuple[int, float, int]:
     ms, cnt = ctypes.c_double(), _i64()
     rc = lib().gls_kernel_time(h, kind, ctypes.byref(ms), ctypes.byref(cnt))
     return rc, ms.value, cnt.value
+
+
+def gls_solve_stream(h, snp_begin, snp_end, block, p_R, fill, fill_ctx, sink, sink_ctx):
+    """fill / sink: C function pointers (ints) or ctypes callbacks of types
+    FILL_FN / SINK_FN.  Returns (return code, gls_stream_stats)."""
+    st = gls_stream_stats()
+    f = ctypes.cast(fill, _p) if not isinstance(fill, int) else fill
+    k = ctypes.cast(sink, _p) if not isinstance(sink, int) else sink
+    rc = lib().gls_solve_stream(h, snp_begin, snp_end, block, p_R, f, fill_ctx, k, sink_ctx,
+                                ctypes.byref(st))
+    return rc, st
 
 
 # ---- torch convenience ---------------------------------------------------------
