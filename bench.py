@@ -38,7 +38,7 @@ PEAK_HBM_GBS = 8000.0
 # the paper's in-core/out-of-core time for n=10^4, p=4, m=10^6 on 12 Xeon
 # cores (Table 3): 816 s, i.e. 1,225 solves/s
 PAPER_BI_PER_S = 1_000_000 / 816.0
-WORKLOADS = {"scale": dg.SCALE, "mixed": dg.MIXED, "stream": dg.STREAM}
+WORKLOADS = {"scale": dg.SCALE, "mixed": dg.MIXED, "stream": dg.STREAM, "serve": dg.SERVE_BASE}
 
 
 def log(*a):
@@ -63,6 +63,10 @@ def parse():
                     help="problems checked against the oracle per form (0 skips)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="budget of the oracle's CPU sample (0 skips it)")
+    ap.add_argument("--serve-jobs", type=int, default=12, help="jobs in the serving mix")
+    ap.add_argument("--serve-load", type=float, default=0.7,
+                    help="offered load of the Poisson arrivals, relative to 50 TFLOP/s")
+    ap.add_argument("--serve-m-max", type=float, default=1e7)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (for scaling HBM counters)")
     return ap.parse_args()
@@ -348,6 +352,50 @@ def stream_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def serve_bench(args):
+    """The serving mix: Poisson arrivals of GWAS jobs (n in {1500, 4000,
+    10000, 20000}, p uniform in 4..20, m log-uniform in [1e5, m_max], each
+    with its own M = h Phi + (1-h) I + 1e-3 I, h ~ U[0.2, 0.8]) through the
+    continuous-batching scheduler, once per precision on the same mix."""
+    import torch
+    from paper_1210_7325_amd import serve
+    torch.cuda.set_device(0)
+    proto = serve.make_jobs(args.serve_jobs, rate=1.0, m_range=(1e5, args.serve_m_max))
+    work = sum(float(j.n) ** 2 * j.m for j in proto)
+    # arrival rate for the requested offered load at 50 TFLOP/s of whitening
+    rate = args.serve_load * 50e12 / (work / len(proto))
+    t0 = time.time()
+    phi = {}
+    for n in sorted({j.n for j in proto}):
+        phi[n] = torch.from_numpy(dg.make_phi(dg.SERVE_BASE.replace(n=n, q=2 * n))).cuda()
+    log(f"Phi for n in {sorted(phi)} built in {time.time() - t0:.1f}s; rate {rate:.3f} jobs/s, "
+        f"{work / 1e15:.2f} PFLOP of whitening")
+    res = {}
+    for prec in args.forms.split(","):
+        jobs = serve.make_jobs(args.serve_jobs, rate=rate, m_range=(1e5, args.serve_m_max))
+        ex = serve.GpuExecutor(precision=prec, phi=phi)
+        stats = serve.Scheduler(ex, budget_bytes=200 << 30).run(jobs)
+        stats["jobs_detail"] = [(j.id, j.n, j.p, j.m, round(j.arrival, 3), round(j.finished - j.arrival, 3)
+                                 if j.finished is not None else None, j.state) for j in jobs]
+        res[prec] = stats
+        log(f"[{prec}] {stats['solves_per_s']:.0f} b_i/s, {stats['whitening_tflops']:.1f} TFLOP/s, "
+            f"latency p50 {stats['latency_p50_s']:.2f}s p99 {stats['latency_p99_s']:.2f}s, "
+            f"{stats['items_per_round']:.1f} items/round, done {stats['done']}/{stats['jobs']}")
+    head = res[args.forms.split(",")[0]]
+    out = {
+        "metric": "GWAS serving mix: solves/s with p50/p99 job latency",
+        "value": round(head["solves_per_s"], 1), "unit": "b_i/s", "n_gpus": 1, "steps": 1,
+        "warmup": 0, "ms_per_step": round(head["makespan_s"] * 1e3, 1), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "serving_mix", "jobs": args.serve_jobs, "arrival_rate": rate,
+                   "offered_load_at_50TF": args.serve_load, "n": [1500, 4000, 10000, 20000],
+                   "p": [4, 20], "m": [1e5, args.serve_m_max], "h": [0.2, 0.8],
+                   "hbm_budget_bytes": 200 << 30, "parallelism": "1 GPU"},
+        "forms": res,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -355,6 +403,9 @@ def main():
         return
     if args.workload == "stream" and args.gpus == 1:
         stream_bench(args)
+        return
+    if args.workload == "serve" and args.gpus == 1:
+        serve_bench(args)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))

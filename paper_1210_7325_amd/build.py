@@ -2,6 +2,7 @@
 
   libgls.so     the solver (HIP kernels for gfx950 + the C ABI of include/gls.h)
   libglsgen.so  the synthetic-input generator (host C, OpenMP)
+  libglsgen_dev.so  its device twin (HIP), for inputs generated in HBM
 
 Run `python -m paper_1210_7325_amd.build` or call build_all().
 """
@@ -62,8 +63,21 @@ def build_gen() -> str:
     return out
 
 
+def build_gen_dev() -> str:
+    """Device twin of the generator (its own library: input generation only)."""
+    os.makedirs(BUILD, exist_ok=True)
+    obj = os.path.join(BUILD, "datagen_dev.hip.o")
+    _run([HIPCC, "-x", "hip", *HIP_FLAGS, "-ffp-contract=off", "-c",
+          os.path.join(CSRC, "datagen_dev.hip"), "-o", obj])
+    tmp = os.path.join(PKG, "libglsgen_dev.so.tmp")
+    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", obj, "-o", tmp])
+    os.replace(tmp, os.path.join(PKG, "libglsgen_dev.so"))
+    return os.path.join(PKG, "libglsgen_dev.so")
+
+
 def build_all() -> None:
     build_gen()
+    build_gen_dev()
     build_gls()
 
 

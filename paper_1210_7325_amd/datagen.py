@@ -97,6 +97,37 @@ def _clib():
     return _CLIB or None
 
 
+_DLIB = None
+
+
+def _dlib():
+    global _DLIB
+    if _DLIB is None:
+        path = os.path.join(os.path.dirname(__file__), "libglsgen_dev.so")
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is not built")
+        lib = ctypes.CDLL(path)
+        lib.gen_genotypes_dev.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                          ctypes.c_double, ctypes.c_double, ctypes.c_int64,
+                                          ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
+                                          ctypes.c_int64, ctypes.c_void_p]
+        lib.gen_genotypes_dev.restype = ctypes.c_int
+        _DLIB = lib
+    return _DLIB
+
+
+def make_XR_device(w: "Workload", snp0: int, nsnp: int, out, stream: int = 0) -> None:
+    """Genotypes of problems snp0.. generated in device memory: `out` is a
+    device int8 column-major (n, >= nsnp*p_R) tensor; `stream` a hipStream_t.
+    Bit-identical to make_XR (the device twin of the same generator)."""
+    assert out.dtype.__str__() == "torch.int8" and out.stride(0) == 1
+    ld = out.stride(1) if out.shape[1] > 1 else w.n
+    rc = _dlib().gen_genotypes_dev(w.seed, S_MAF_R, S_XR, w.maf_R[0], w.maf_R[1], w.n,
+                                   snp0 * w.p_R, nsnp * w.p_R, out.data_ptr(), ld, stream)
+    if rc != 0:
+        raise RuntimeError(f"gen_genotypes_dev failed ({rc})")
+
+
 def maf(seed: int, stream: int, lo: float, hi: float, col0: int, ncols: int,
         use_c: Optional[bool] = None) -> np.ndarray:
     """Minor-allele frequencies f_j = lo + (hi - lo) * u_j of columns col0.."""

@@ -1,0 +1,150 @@
+"""The serving scheduler's logic on a simulated device (no GPU): admission by
+footprint, continuous batching of blocks from several jobs, completion
+bookkeeping, failure isolation and latency accounting."""
+import numpy as np
+import pytest
+
+from paper_1210_7325_amd import serve
+
+
+class VirtualClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def now(self):
+        return self.t
+
+    def sleep(self, dt):
+        self.t += max(dt, 1e-4)
+
+
+class FakeDevice(serve.Executor):
+    """One device: a round takes as long as its most expensive item
+    (n^2 * nsnp / rate), rounds run one after another."""
+
+    def __init__(self, clock, rate=1e12, bad=()):
+        self.clock = clock
+        self.rate = rate
+        self.bad = set(bad)
+        self.busy_until = 0.0
+        self.rounds = []
+        self.resident = set()
+        self.max_resident = 0
+
+    def footprint(self, job):
+        return job.n * job.n * 8 + job.n * job.block + job.m * job.p * 8
+
+    def admit(self, job):
+        if job.id in self.bad:
+            raise RuntimeError("M is not positive definite")
+        self.resident.add(job.id)
+        self.max_resident = max(self.max_resident, len(self.resident))
+
+    def submit_round(self, items):
+        cost = max(j.n * j.n * nsnp for (j, s, nsnp) in items) / self.rate
+        start = max(self.clock.now(), self.busy_until)
+        self.busy_until = start + cost
+        self.rounds.append([(j.id, s, nsnp) for (j, s, nsnp) in items])
+        return self.busy_until
+
+    def poll(self, token):
+        return self.clock.now() >= token
+
+    def wait(self, token):
+        if self.clock.now() < token:
+            self.clock.t = token
+
+    def release(self, job):
+        self.resident.discard(job.id)
+
+
+def run(jobs, budget, bad=(), max_items=16):
+    clock = VirtualClock()
+    dev = FakeDevice(clock, bad=bad)
+    sched = serve.Scheduler(dev, budget, max_items=max_items, clock=clock.now, sleep=clock.sleep)
+    stats = sched.run(jobs)
+    return stats, dev, sched
+
+
+def test_job_mix_is_reproducible_and_in_range():
+    a = serve.make_jobs(50, rate=0.2)
+    b = serve.make_jobs(50, rate=0.2)
+    assert [(j.arrival, j.n, j.p, j.m, j.h) for j in a] == [(j.arrival, j.n, j.p, j.m, j.h) for j in b]
+    assert all(j.n in (1500, 4000, 10000, 20000) for j in a)
+    assert all(4 <= j.p <= 20 for j in a)
+    assert all(1e5 <= j.m <= 1e7 for j in a)
+    assert all(0.2 <= j.h <= 0.8 for j in a)
+    gaps = np.diff([0.0] + [j.arrival for j in a])
+    assert np.all(gaps > 0) and 2.0 < gaps.mean() < 8.0   # rate 0.2/s
+    assert len({j.n for j in a}) == 4 and len({j.p for j in a}) > 8
+
+
+def test_block_sizes_equalize_work():
+    for n in (1500, 4000, 10000, 20000):
+        b = serve.job_block(n)
+        assert b % 64 == 0 and 256 <= b <= 65536
+    assert serve.job_block(10000) == 4096
+    assert serve.job_block(20000) == 1024
+
+
+def small_jobs():
+    return [serve.Job(id=i, arrival=0.001 * i, n=n, p=4, m=m, h=0.5, seed=i, block=1024)
+            for i, (n, m) in enumerate([(1000, 20000), (2000, 9000), (1000, 5000), (3000, 4000),
+                                        (1500, 8000)])]
+
+
+def test_all_jobs_complete_and_batches_mix_jobs():
+    jobs = small_jobs()
+    stats, dev, sched = run(jobs, budget=10 ** 12)
+    assert stats["done"] == len(jobs) and stats["failed"] == 0
+    for j in jobs:
+        assert j.completed == j.m and j.state == "done"
+        assert j.finished >= j.admitted >= j.arrival
+    # every problem submitted exactly once, in order per job
+    seen = {}
+    for rnd in dev.rounds:
+        ids = [i for (i, s, nsnp) in rnd]
+        assert len(ids) == len(set(ids))      # one item per job per round
+        for (i, s, nsnp) in rnd:
+            assert s == seen.get(i, 0)
+            seen[i] = s + nsnp
+    assert all(seen[j.id] == j.m for j in jobs)
+    assert max(len(r) for r in dev.rounds) == len(jobs)  # continuous batching
+
+
+def test_admission_respects_the_memory_budget():
+    jobs = small_jobs()
+    fp = FakeDevice(VirtualClock()).footprint
+    budget = fp(jobs[3]) + fp(jobs[1]) + 1   # room for about two jobs
+    stats, dev, sched = run(jobs, budget=budget)
+    assert stats["done"] == len(jobs)
+    assert sched.peak_used <= budget
+    assert dev.max_resident < len(jobs)
+    # later arrivals waited for memory
+    assert stats["admission_wait_p99_s"] > 0
+
+
+def test_failed_job_is_isolated():
+    jobs = small_jobs()
+    stats, dev, sched = run(jobs, budget=10 ** 12, bad={2})
+    assert jobs[2].state == "failed" and "positive definite" in jobs[2].error
+    assert stats["done"] == len(jobs) - 1
+    assert all(j.completed == j.m for j in jobs if j.id != 2)
+
+
+def test_job_larger_than_budget_fails_without_blocking_others():
+    jobs = small_jobs()
+    big = serve.Job(id=99, arrival=0.0, n=50000, p=4, m=100, h=0.5, seed=1)
+    stats, dev, sched = run(jobs + [big], budget=10 ** 10)
+    assert big.state == "failed" and "exceeds" in big.error
+    assert stats["done"] == len(jobs)
+
+
+def test_latency_accounting_on_an_idle_device():
+    job = serve.Job(id=0, arrival=5.0, n=1000, p=4, m=4096, h=0.5, seed=0)
+    stats, dev, sched = run([job], budget=10 ** 12)
+    expect = 1000 ** 2 * serve.job_block(1000) / 1e12
+    cost = sum(1000 ** 2 * nsnp for r in dev.rounds for (_, _, nsnp) in r) / 1e12
+    assert job.finished - job.arrival == pytest.approx(cost, rel=1e-6, abs=1e-3)
+    assert stats["latency_p50_s"] == pytest.approx(job.finished - job.arrival)
+    assert expect > 0
