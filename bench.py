@@ -63,10 +63,11 @@ def parse():
                     help="problems checked against the oracle per form (0 skips)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="budget of the oracle's CPU sample (0 skips it)")
-    ap.add_argument("--serve-jobs", type=int, default=12, help="jobs in the serving mix")
+    ap.add_argument("--serve-jobs", type=int, default=16, help="jobs in the serving mix")
     ap.add_argument("--serve-load", type=float, default=0.7,
                     help="offered load of the Poisson arrivals, relative to 50 TFLOP/s")
-    ap.add_argument("--serve-m-max", type=float, default=1e7)
+    ap.add_argument("--serve-m-max", type=float, default=2e6,
+                    help="upper end of the log-uniform m range (the full mix uses 1e7)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (for scaling HBM counters)")
     return ap.parse_args()
@@ -374,9 +375,10 @@ def serve_bench(args):
     for prec in args.forms.split(","):
         jobs = serve.make_jobs(args.serve_jobs, rate=rate, m_range=(1e5, args.serve_m_max))
         ex = serve.GpuExecutor(precision=prec, phi=phi)
-        stats = serve.Scheduler(ex, budget_bytes=200 << 30).run(jobs)
+        stats = serve.Scheduler(ex, budget_bytes=200 << 30,
+                                log=lambda msg, prec=prec: log(f"[{prec}] {msg}")).run(jobs)
         stats["jobs_detail"] = [(j.id, j.n, j.p, j.m, round(j.arrival, 3), round(j.finished - j.arrival, 3)
-                                 if j.finished is not None else None, j.state) for j in jobs]
+                                 if j.finished is not None else None, j.state, j.error) for j in jobs]
         res[prec] = stats
         log(f"[{prec}] {stats['solves_per_s']:.0f} b_i/s, {stats['whitening_tflops']:.1f} TFLOP/s, "
             f"latency p50 {stats['latency_p50_s']:.2f}s p99 {stats['latency_p99_s']:.2f}s, "

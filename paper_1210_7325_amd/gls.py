@@ -10,7 +10,9 @@ Two levels:
     (pointers and streams as Python ints), raising GLSError on failure;
   * Cohort, a small convenience class over torch tensors.
 
-Matrices are column-major: a (rows, cols) tensor with stride(0) == 1.
+Matrices are column-major: a (rows, cols) tensor with stride(0) == 1; other
+layouts are copied first, on the handle's stream, so that the copy is ordered
+before the library's kernels.
 """
 from __future__ import annotations
 
@@ -238,7 +240,9 @@ class Cohort:
             self.n = None
             return
         assert M.dtype == torch.float64 and M.is_cuda and M.dim() == 2 and M.shape[0] == M.shape[1]
-        M = colmajor(M)
+        # any layout copy runs on the handle's stream, ahead of the factorization
+        with torch.cuda.stream(self.stream):
+            M = colmajor(M)
         self.n = int(M.shape[0])
         rc, h = gls_factor(self.n, M.data_ptr(), _ld(M), self.prec, _stream_ptr(self.stream))
         self.h = h
@@ -254,8 +258,9 @@ class Cohort:
     # the fixed part (X_L, y) -------------------------------------------------
     def whiten_fixed(self, XL, Y, intercept_col: int = 0):
         torch = _torch()
-        XL = colmajor(XL.to(torch.float64))
-        Y = colmajor(Y.to(torch.float64))
+        with torch.cuda.stream(self.stream):
+            XL = colmajor(XL.to(torch.float64))
+            Y = colmajor(Y.to(torch.float64))
         self.p_L, self.t = int(XL.shape[1]), int(Y.shape[1])
         _chk(gls_whiten_fixed(self.h, self.p_L, XL.data_ptr(), _ld(XL), self.t, Y.data_ptr(),
                               _ld(Y), intercept_col), "gls_whiten_fixed")
@@ -273,40 +278,44 @@ class Cohort:
         (B, info) with B of shape (nsnp, t, p) FP64 and info int32 (nsnp,)."""
         torch = _torch()
         assert XR.dtype == torch.int8 and XR.is_cuda
-        XR = colmajor(XR)
-        ncols = int(XR.shape[1])
-        assert ncols % p_R == 0
-        nsnp = ncols // p_R
-        p = self.p_L + p_R
-        if B is None:
-            B = torch.empty((nsnp, self.t, p), dtype=torch.float64, device=XR.device)
-        if info is None:
-            info = torch.empty((nsnp,), dtype=torch.int32, device=XR.device)
+        with torch.cuda.stream(self.stream):
+            XR = colmajor(XR)
+            ncols = int(XR.shape[1])
+            assert ncols % p_R == 0
+            nsnp = ncols // p_R
+            p = self.p_L + p_R
+            if B is None:
+                B = torch.empty((nsnp, self.t, p), dtype=torch.float64, device=XR.device)
+            if info is None:
+                info = torch.empty((nsnp,), dtype=torch.int32, device=XR.device)
         _chk(gls_solve_block(self.h, nsnp, p_R, XR.data_ptr(), _ld(XR), B.data_ptr(), p,
                              info.data_ptr()), "gls_solve_block")
         return B, info
 
     def whiten_block(self, X):
         torch = _torch()
-        X = colmajor(X)
-        W = torch.empty((X.shape[1], X.shape[0]), dtype=torch.float64, device=X.device).t()
+        with torch.cuda.stream(self.stream):
+            X = colmajor(X)
+            W = torch.empty((X.shape[1], X.shape[0]), dtype=torch.float64, device=X.device).t()
         _chk(gls_whiten_block(self.h, int(X.shape[1]), X.data_ptr(), _ld(X), W.data_ptr(),
                               int(X.shape[0])), "gls_whiten_block")
         return W
 
     def copy_factor(self):
         torch = _torch()
-        L = torch.empty((self.n, self.n), dtype=torch.float64, device="cuda").t()
+        with torch.cuda.stream(self.stream):
+            L = torch.empty((self.n, self.n), dtype=torch.float64, device="cuda").t()
         _chk(gls_copy_factor(self.h, L.data_ptr(), self.n), "gls_copy_factor")
         return L
 
     def copy_fixed(self):
         torch = _torch()
         n, pL, t = self.n, self.p_L, self.t
-        WL = torch.empty((pL, n), dtype=torch.float64, device="cuda").t()
-        Yt = torch.empty((t, n), dtype=torch.float64, device="cuda").t()
-        STL = torch.empty((pL, pL), dtype=torch.float64, device="cuda").t()
-        CT = torch.empty((t, pL), dtype=torch.float64, device="cuda").t()
+        with torch.cuda.stream(self.stream):
+            WL = torch.empty((pL, n), dtype=torch.float64, device="cuda").t()
+            Yt = torch.empty((t, n), dtype=torch.float64, device="cuda").t()
+            STL = torch.empty((pL, pL), dtype=torch.float64, device="cuda").t()
+            CT = torch.empty((t, pL), dtype=torch.float64, device="cuda").t()
         _chk(gls_copy_fixed(self.h, WL.data_ptr(), n, Yt.data_ptr(), n, STL.data_ptr(),
                             CT.data_ptr()), "gls_copy_fixed")
         return WL, Yt, STL, CT

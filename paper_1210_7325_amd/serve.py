@@ -40,7 +40,8 @@ class Job:
     h: float
     seed: int
     # filled in by the scheduler
-    block: int = 0
+    block: int = 0          # problems per item when the device is shared
+    max_block: int = 0      # largest item (when few jobs share the device)
     state: str = "pending"  # pending -> active -> done | failed
     admitted: Optional[float] = None
     finished: Optional[float] = None
@@ -111,13 +112,20 @@ class Scheduler:
     """Admission by footprint, round composition, completion bookkeeping."""
 
     def __init__(self, executor: Executor, budget_bytes: int, max_items: int = 16,
-                 inflight: int = 2, clock=time.monotonic, sleep=time.sleep):
+                 inflight: int = 2, clock=time.monotonic, sleep=time.sleep,
+                 target_cols: int = 16384, max_mult: int = 16, log=None):
         self.ex = executor
         self.budget = int(budget_bytes)
         self.max_items = max_items
         self.inflight = inflight
         self.clock = clock
         self.sleep = sleep
+        # a round should give the device at least target_cols genotype
+        # columns; with few active jobs every job's item grows by a common
+        # factor (up to max_mult), which keeps the items of a round equal
+        self.target_cols = target_cols
+        self.max_mult = max_mult
+        self.log = log
         self.used = 0
         self.peak_used = 0
         self.rounds = 0
@@ -127,6 +135,7 @@ class Scheduler:
         jobs = sorted(jobs, key=lambda j: j.arrival)
         for j in jobs:
             j.block = j.block or job_block(j.n)
+            j.max_block = j.max_block or min(max(j.block, 65536), j.block * self.max_mult)
         t0 = self.clock()
         arrived: List[Job] = []
         active: List[Job] = []
@@ -152,23 +161,30 @@ class Scheduler:
                 try:
                     self.ex.admit(j)
                 except Exception as e:  # isolate the failure to this job
-                    j.state, j.error = "failed", str(e)
+                    j.state, j.error = "failed", f"{type(e).__name__}: {e}"
                     j.finished = self.clock() - t0
+                    if self.log:
+                        self.log(f"t={j.finished:.2f}s job {j.id} failed at admission: {j.error}")
                     continue
                 j.state, j.admitted = "active", self.clock() - t0
                 j._need = need
                 self.used += need
                 self.peak_used = max(self.peak_used, self.used)
                 active.append(j)
+                if self.log:
+                    self.log(f"t={j.admitted:.2f}s admit job {j.id} (n={j.n}, p={j.p}, m={j.m}), "
+                             f"{len(active)} active, {self.used / 2**30:.1f} GiB used")
             # compose and queue a round
             if len(queue) < self.inflight:
                 ready = [j for j in active if j.submitted < j.m]
                 if ready:
                     items = []
                     k = len(ready)
-                    for i in range(min(k, self.max_items)):
-                        j = ready[(rr + i) % k]
-                        nsnp = min(j.block, j.m - j.submitted)
+                    pick = [ready[(rr + i) % k] for i in range(min(k, self.max_items))]
+                    base = sum(j.block for j in pick)
+                    mult = max(1, min(self.max_mult, -(-self.target_cols // base)))
+                    for j in pick:
+                        nsnp = min(j.block * mult, j.max_block, j.m - j.submitted)
                         items.append((j, j.submitted, nsnp))
                         j.submitted += nsnp
                     rr = (rr + len(items)) % max(k, 1)
@@ -189,6 +205,9 @@ class Scheduler:
                         self.ex.release(j)
                         self.used -= j._need
                         active.remove(j)
+                        if self.log:
+                            self.log(f"t={fin:.2f}s job {j.id} done, latency "
+                                     f"{fin - j.arrival:.2f}s, {len(active)} active")
                 progressed = True
             if progressed:
                 continue
@@ -263,8 +282,9 @@ class GpuExecutor(Executor):
 
     def footprint(self, job: Job) -> int:
         p = self.gls.PRECISIONS[self.precision]
-        b = self.gls.gls_footprint_bytes(job.n, job.p_L, 1, job.block or job_block(job.n), p)
-        b += job.n * (job.block or job_block(job.n))          # genotype block
+        blk = job.max_block or job.block or job_block(job.n)
+        b = self.gls.gls_footprint_bytes(job.n, job.p_L, 1, blk, p)
+        b += job.n * blk                                       # genotype block
         b += job.m * job.p * 8 + job.m * 4                     # b and info
         b += job.n * job.n * 8                                 # M while factoring
         return int(b)
@@ -274,18 +294,21 @@ class GpuExecutor(Executor):
         w = job.workload()
         s = torch.cuda.Stream()
         with torch.cuda.stream(s):
-            M = self._phi(job.n) * job.h
+            phi = self._phi(job.n)
+            # column-major like phi (which is symmetric): no layout copy later
+            M = torch.empty_strided(phi.shape, (1, phi.shape[0]), dtype=phi.dtype, device=phi.device)
+            torch.mul(phi, job.h, out=M)
             M.diagonal().add_(1.0 - job.h + w.diag_shift)
-            M = M.t()  # column-major view of the symmetric matrix
-        XL = torch.from_numpy(np.asfortranarray(dg.make_XL(w))).cuda()
-        Y = torch.from_numpy(np.asfortranarray(dg.make_Y(w))).cuda()
+            XL = torch.from_numpy(np.asfortranarray(dg.make_XL(w))).cuda()
+            Y = torch.from_numpy(np.asfortranarray(dg.make_Y(w))).cuda()
         s.synchronize()
         c = gls.Cohort(M, precision=self.precision, stream=s)
         del M
         c.whiten_fixed(XL, Y, intercept_col=0)
-        c.reserve(job.block)
+        blk = job.max_block or job.block
+        c.reserve(blk)
         s.synchronize()
-        xbuf = torch.empty((job.block, job.n), dtype=torch.int8, device="cuda").t()
+        xbuf = torch.empty((blk, job.n), dtype=torch.int8, device="cuda").t()
         B = torch.empty((job.m, 1, job.p), dtype=torch.float64, device="cuda")
         info = torch.empty((job.m,), dtype=torch.int32, device="cuda")
         self.state[job.id] = (c, xbuf, B, info, w)

@@ -238,3 +238,26 @@ def test_full_scale_sampled_in_bench_configuration(G):
     say("full scale sampled max rel err", err.max())
     assert err.max() < TOL_B
     del dXR
+
+
+def test_layout_copies_are_ordered_on_the_handle_stream(G):
+    """Row-major inputs are copied to column-major on the handle's own stream
+    before the library's kernels read them (the copy used to run on the
+    current stream and could race a factorization on a side stream)."""
+    say("row-major inputs on a side stream")
+    w, M, XL, Y, XR = small_problem(3000, pL=4, m=200, seed=31)
+    side = torch.cuda.Stream()
+    Lref = orc.cholesky_lower(M)
+    ref = orc.gls_sequence(M, XL, XR, Y, 1)
+    for rep in range(3):
+        Mr = torch.from_numpy(np.ascontiguousarray(M)).cuda()        # row-major
+        XLr = torch.from_numpy(np.ascontiguousarray(XL)).cuda()
+        Yr = torch.from_numpy(np.ascontiguousarray(Y)).cuda()
+        XRr = torch.from_numpy(np.ascontiguousarray(XR)).cuda()
+        torch.cuda.synchronize()
+        c = G.Cohort(Mr, stream=side).whiten_fixed(XLr, Yr)
+        B, info = c.solve_block(XRr)
+        side.synchronize()
+        assert maxrel(c.copy_factor().cpu().numpy(), Lref) < TOL_MID
+        assert orc.relative_error(B.cpu().numpy(), ref).max() < TOL_B
+        c.free()

@@ -32,7 +32,7 @@ class FakeDevice(serve.Executor):
         self.max_resident = 0
 
     def footprint(self, job):
-        return job.n * job.n * 8 + job.n * job.block + job.m * job.p * 8
+        return job.n * job.n * 8 + job.n * job.max_block + job.m * job.p * 8
 
     def admit(self, job):
         if job.id in self.bad:
@@ -58,10 +58,11 @@ class FakeDevice(serve.Executor):
         self.resident.discard(job.id)
 
 
-def run(jobs, budget, bad=(), max_items=16):
+def run(jobs, budget, bad=(), max_items=16, target_cols=16384):
     clock = VirtualClock()
     dev = FakeDevice(clock, bad=bad)
-    sched = serve.Scheduler(dev, budget, max_items=max_items, clock=clock.now, sleep=clock.sleep)
+    sched = serve.Scheduler(dev, budget, max_items=max_items, clock=clock.now, sleep=clock.sleep,
+                            target_cols=target_cols)
     stats = sched.run(jobs)
     return stats, dev, sched
 
@@ -88,14 +89,15 @@ def test_block_sizes_equalize_work():
 
 
 def small_jobs():
-    return [serve.Job(id=i, arrival=0.001 * i, n=n, p=4, m=m, h=0.5, seed=i, block=1024)
+    return [serve.Job(id=i, arrival=0.001 * i, n=n, p=4, m=m, h=0.5, seed=i, block=1024,
+                      max_block=8192)
             for i, (n, m) in enumerate([(1000, 20000), (2000, 9000), (1000, 5000), (3000, 4000),
                                         (1500, 8000)])]
 
 
 def test_all_jobs_complete_and_batches_mix_jobs():
     jobs = small_jobs()
-    stats, dev, sched = run(jobs, budget=10 ** 12)
+    stats, dev, sched = run(jobs, budget=10 ** 12, target_cols=1024)
     assert stats["done"] == len(jobs) and stats["failed"] == 0
     for j in jobs:
         assert j.completed == j.m and j.state == "done"
@@ -138,6 +140,20 @@ def test_job_larger_than_budget_fails_without_blocking_others():
     stats, dev, sched = run(jobs + [big], budget=10 ** 10)
     assert big.state == "failed" and "exceeds" in big.error
     assert stats["done"] == len(jobs)
+
+
+def test_rounds_grow_items_when_few_jobs_share_the_device():
+    jobs = small_jobs()
+    stats, dev, sched = run(jobs, budget=10 ** 12, target_cols=8192)
+    for rnd in dev.rounds:
+        sizes = {i: nsnp for (i, s, nsnp) in rnd}
+        full = [nsnp for (i, s, nsnp) in rnd if s + nsnp < jobs[i].m]   # not a job's last item
+        if full:
+            assert len(set(full)) == 1                   # one common multiple per round
+            # the common item size times the items would reach the target
+            assert len(rnd) * max(full) >= 8192 or max(full) == jobs[0].max_block
+    alone = [r for r in dev.rounds if len(r) == 1]
+    assert alone and max(n for r in alone for (_, _, n) in r) > 1024
 
 
 def test_latency_accounting_on_an_idle_device():
