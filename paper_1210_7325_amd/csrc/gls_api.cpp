@@ -234,12 +234,13 @@ int launch_items(const gls_work* items, int64_t count, hipStream_t st, gls_handl
     const int64_t ncols = w.nsnp * w.p_R;
     if (refine) {
       xt.j[xt.njobs++] = make_xz(w.h, xgroups, ncols, w.X_R, w.ldxr);
-      xgroups += (ncols + 15) / 16;
+      xgroups += (ncols + AS_GROUP_COLS - 1) / AS_GROUP_COLS;
     }
     tab.j[tab.njobs++] = make_job(w.h, slabs, ncols, w.X_R, w.ldxr);
     slabs += (ncols + C - 1) / C;
     at.j[at.njobs++] = make_asm(w.h, groups, w.nsnp, w.p_R, w.B, w.ldb, w.info);
-    groups += (w.nsnp + 16 / w.p_R - 1) / (16 / w.p_R);
+    const int64_t per_group = (AS_GROUP_COLS / 16) * (16 / w.p_R);  // problems per assembly work-group
+    groups += (w.nsnp + per_group - 1) / per_group;
   }
   if (tab.njobs == 0) return GLS_OK;
   hipStream_t keep = th->stream;

@@ -10,6 +10,7 @@ constexpr int DEFAULT_C = 64; // default slab width for genotype blocks (16, 32 
 constexpr int MAXP = 20;      // p = p_L + p_R <= 20 (Sec. 1)
 constexpr int MAXT = 8;       // phenotypes per call
 constexpr int MAX_INLINE_JOBS = 16;
+constexpr int AS_GROUP_COLS = 64;  // columns per work-group of the assembly and centering kernels
 #ifndef GLS_TRSM_DEPTH
 #define GLS_TRSM_DEPTH 4
 #endif
@@ -68,7 +69,7 @@ struct AsmTable {
 // Centering pre-pass of the FP32_REFINE form: per genotype column the exact
 // dyadic shift s = round(256 mean(x)) / 256 and (x - s)^T Z.
 struct XzDesc {
-  int64_t grp0;             // first work-group (16 columns each)
+  int64_t grp0;             // first work-group (AS_GROUP_COLS columns each)
   int64_t n;
   int64_t ncols;
   const int8_t* X;

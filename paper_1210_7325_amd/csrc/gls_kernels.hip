@@ -26,6 +26,8 @@
 #include <stdint.h>
 #include <math.h>
 
+#include <algorithm>
+
 #include "gls_internal.h"
 
 typedef double d4 __attribute__((ext_vector_type(4)));
@@ -589,16 +591,27 @@ __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ F, int6
 // a3/a4: per-problem assembly and solve (Alg. 5 loop body: S_BL_i, S_BR_i,
 // b_B_i by gemv/dot, then posv of the p x p system; Fig. 1 partition).
 //
-// One work-group per group of G = 16 / p_R problems (G p_R <= 16 columns).
-// Lane (rg, cl) of wave w reads W(4s + rg, col0 + cl) for s = w, w+NW, ...
-// (512 contiguous bytes per wave and step in the slab layout) and keeps
-// dot products with the rows of F = [W_L | ytil] and with the other
-// columns of its problem.  After a fixed-order reduction the p x p system
-// S_i = [S_TL, S_BL_i^T; S_BL_i, S_BR_i] and c_i = [C_T; C_B_i] are built in
-// LDS and each problem is solved by one wavefront: Cholesky, forward and
-// backward substitution with lane j holding column j of S_i and row j of
-// c_i, and wave-wide broadcasts (v_readlane) between the steps.
+// One work-group per group of problems laid out in 4 tiles of 16 columns,
+// PT = floor(16 / p_R) problems per tile (a problem never straddles two
+// tiles).  The per-column dot products are small products on FP64 MFMA:
+// per tile and 4-row k-step, A = W^T (16 columns x 4 rows) is exactly what a
+// lane holds in the slab layout (lane l: W[4s + l/16][16ct + l%16]), and
+//   D_F  += A  F[4s .. 4s+3][16 et .. 16 et + 15]       (W^T [W_L | ytil])
+//   D_G  += A  W[4s .. 4s+3][tile]                       (W^T W of the tile)
+// where the Gram's B operand is the same register as A.  Wave w takes the
+// row octets w, w + 8, ... (one 16-byte pair per tile per octet, i.e. two
+// k-steps; as_depth<ET>() octets in flight).  The per-wave products are reduced
+// in LDS in a fixed order; then each problem is solved by one wavefront:
+// Cholesky, forward and backward substitution with lane j holding column j
+// of S_i and row j of c_i, and wave-wide broadcasts (v_readlane) between
+// the steps.  Every sum runs over the rows in an order fixed by the row
+// index alone, so a column's result does not depend on which group, launch
+// or slab width it is solved in.
 constexpr int AS_WAVES = 8;
+constexpr int AS_COLS = AS_GROUP_COLS;     // columns per work-group (4 tiles of 16)
+// row octets in flight per wave (fewer with two F tiles: registers)
+template <int ET> constexpr int as_depth() { return ET == 1 ? 4 : 3; }
+constexpr int AS_DOTS = 2 * 16 + 16;       // per column: up to 32 F dots + 16 Gram entries
 
 // Cholesky of a p x p SPD matrix held by one wavefront, lane j holding
 // column j (col[a] = S[a][j]).  On return lane j holds column j of the
@@ -672,6 +685,102 @@ __device__ __forceinline__ void wave_cholsolve(const double (&col)[MAXP], double
   }
 }
 
+// Products of the 64 columns of a group with the rows of F (ET tiles of 16
+// columns of F, zero past ldf) and, if GRAM, the Gram matrix of each column
+// tile, accumulated per wave on FP64 MFMA.  loadA(ct, o) gives the lane's
+// A-operand pair of tile ct for row octet o: rows 8o + l/16 (.x) and
+// 8o + 4 + l/16 (.y) of column l%16.  F: row-major, ld = ldf, at least
+// 8 noct rows.  acc[ct][et] (et < ET) and acc[ct][ET] (Gram) use the MFMA
+// output layout: lane l, element i = row l/16 + 4i (a column of the tile),
+// column l%16.
+template <int ET, bool GRAM, class LoadA>
+__device__ __forceinline__ void mfma_dots(LoadA loadA, const double* __restrict__ F, int ldf,
+                                          int64_t noct, int wave, int lane,
+                                          d4 (&acc)[4][ET + 1]) {
+  const int r = lane / 16, cl = lane % 16;
+#pragma unroll
+  for (int ct = 0; ct < 4; ct++)
+#pragma unroll
+    for (int et = 0; et <= ET; et++) acc[ct][et] = d4{0.0, 0.0, 0.0, 0.0};
+  constexpr int DEPTH = as_depth<ET>();
+  d2 av[DEPTH][4];
+  double f0[DEPTH][ET], f1[DEPTH][ET];
+  auto fetch = [&](int64_t o, d2 (&a)[4], double (&g0)[ET], double (&g1)[ET])
+      __attribute__((always_inline)) {
+#pragma unroll
+    for (int ct = 0; ct < 4; ct++) a[ct] = loadA(ct, o);
+    const double* __restrict__ p0 = F + (8 * o + r) * ldf;
+    const double* __restrict__ p1 = p0 + 4 * ldf;
+#pragma unroll
+    for (int et = 0; et < ET; et++) {
+      const int e = 16 * et + cl;
+      g0[et] = e < ldf ? p0[e] : 0.0;
+      g1[et] = e < ldf ? p1[e] : 0.0;
+    }
+  };
+#pragma unroll
+  for (int st = 0; st < DEPTH; st++)
+    if (wave + 8 * st < noct) fetch(wave + 8 * st, av[st], f0[st], f1[st]);
+  for (int64_t o0 = wave; o0 < noct; o0 += 8 * DEPTH) {
+#pragma unroll
+    for (int st = 0; st < DEPTH; st++) {
+      const int64_t o = o0 + 8 * st;
+      if (o < noct) {
+#pragma unroll
+        for (int ct = 0; ct < 4; ct++) {
+#pragma unroll
+          for (int et = 0; et < ET; et++) {
+            acc[ct][et] = MFMA64(av[st][ct].x, f0[st][et], acc[ct][et]);
+            acc[ct][et] = MFMA64(av[st][ct].y, f1[st][et], acc[ct][et]);
+          }
+          if (GRAM) {
+            acc[ct][ET] = MFMA64(av[st][ct].x, av[st][ct].x, acc[ct][ET]);
+            acc[ct][ET] = MFMA64(av[st][ct].y, av[st][ct].y, acc[ct][ET]);
+          }
+        }
+        const int64_t on = o + 8 * DEPTH;
+        if (on < noct) fetch(on, av[st], f0[st], f1[st]);
+      }
+    }
+  }
+}
+
+// Fixed-order sum over the waves of one 16-wide slice of the products:
+// slice et of every tile lands in red, then dots[c][16 et + e] (e < elim)
+// or, for the Gram slice (gram_pR > 0), dots[c][base + q] = G[c][c0 + q]
+// for q < gram_pR, c0 the first column of c's problem in its tile.
+template <int ET>
+__device__ __forceinline__ void reduce_slice(const d4 (&acc)[4][ET + 1], int et, int wave, int lane,
+                                             double (*red)[AS_COLS][17],
+                                             double (*dots)[AS_DOTS], int elim, int base,
+                                             int gram_pR) {
+  const int r = lane / 16, cl = lane % 16;
+#pragma unroll
+  for (int ct = 0; ct < 4; ct++)
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+      for (int k = 0; k <= ET; k++)
+        if (k == et) red[wave][16 * ct + r + 4 * i][cl] = acc[ct][k][i];
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < AS_COLS * 16; idx += 64 * AS_WAVES) {
+    const int c = idx / 16, e = idx % 16;
+    if (gram_pR == 0) {
+      if (16 * et + e < elim) {
+        double v = 0.0;
+        for (int w = 0; w < AS_WAVES; w++) v += red[w][c][e];
+        dots[c][16 * et + e] = v;
+      }
+    } else if (e < gram_pR && c % 16 < 16 / gram_pR * gram_pR) {   // columns of a problem
+      const int c0 = (c % 16) - (c % 16) % gram_pR;   // problem's first column in the tile
+      double v = 0.0;
+      for (int w = 0; w < AS_WAVES; w++) v += red[w][c][c0 + e];
+      dots[c][base + e] = v;
+    }
+  }
+  __syncthreads();
+}
+
 // REFINE = false: the FP64 path.  REFINE = true: the FP32_REFINE form; the
 // whitened columns are those of the centered genotypes x' = x - s, S^(0) and
 // c^(0) come from them, and one FP64 refinement step on the normal
@@ -679,107 +788,63 @@ __device__ __forceinline__ void wave_cholsolve(const double (&col)[MAXP], double
 // E = x'^T Z_L and e_y = x'^T Z_y exact to FP64 rounding (Z = M^{-1}[X_L|Y]):
 //   r = c' - S' b0,  d = (G G^T)^{-1} r,  b' = b0 + d,
 // then b_L[icol] -= s^T b'_R undoes the centering.
-template <bool REFINE>
+template <bool REFINE, int ET>
 __global__ __launch_bounds__(64 * AS_WAVES) void k_assemble_solve(const AsmTable tab) {
-  __shared__ double red[AS_WAVES][16][MAXP + MAXT + 16];
-  __shared__ double Ssh[16][MAXP * MAXP];
-  __shared__ double Csh[16][MAXP * MAXT];
+  __shared__ double red[AS_WAVES][AS_COLS][17];
+  __shared__ double dots[AS_COLS][AS_DOTS];
 
   int jb = 0;
   while (jb + 1 < tab.njobs && (int64_t)blockIdx.x >= tab.j[jb + 1].grp0) jb++;
   const AsmDesc& J = tab.j[jb];
   const int pL = J.pL, pR = J.pR, t = J.t, p = pL + pR;
-  const int G = 16 / pR;
-  const int64_t grp = (int64_t)blockIdx.x - J.grp0;
-  const int64_t snp0 = grp * G;
-  const int ng = (int)((J.nsnp - snp0) < G ? (J.nsnp - snp0) : G);
-  const int nc = ng * pR;
-  const int64_t col0 = snp0 * pR;
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const int rg = lane / 16, cl = lane % 16;
-  const bool valid = cl < nc;
-  const int q = valid ? cl % pR : 0;
-  const int first = rg * 16 + (valid ? cl - q : 0);
   const int ldf = pL + t;
+  const int PT = 16 / pR;                   // problems per tile
+  const int G = 4 * PT;                     // problems per group
+  const int64_t snp0 = ((int64_t)blockIdx.x - J.grp0) * G;
+  const int ng = (int)((J.nsnp - snp0) < G ? (J.nsnp - snp0) : G);
+  const int64_t col0 = snp0 * pR;           // first genotype column of the group
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+  const int lane = threadIdx.x % 64;
+  const int r = lane / 16, cl = lane % 16;
 
-  double acc[MAXP + MAXT + 16];
+  // lane (r, cl) of tile ct reads column col0 + (ct PT) pR + cl when that is
+  // a column of the group, else column col0 (its products are not used)
+  size_t base[4];
 #pragma unroll
-  for (int e = 0; e < MAXP + MAXT + 16; e++) acc[e] = 0.0;
-
-  const int64_t nsteps = (J.n + 3) / 4;
-  const int64_t mycol = col0 + (valid ? cl : 0);
-  for (int64_t s = wave; s < nsteps; s += AS_WAVES) {
-    const int64_t row = 4 * s + rg;
-    const double w = valid ? J.W[slab_index(row, mycol, J.C, J.n_pad)] : 0.0;
-    const double* __restrict__ f = J.F + row * ldf;
-#pragma unroll
-    for (int e = 0; e < MAXP + MAXT; e++)
-      if (e < ldf) acc[e] += w * f[e];
-#pragma unroll
-    for (int e = 0; e < 16; e++)
-      if (e < pR) {
-        int src = first + e;
-        src = src < rg * 16 + 15 ? src : rg * 16 + 15;
-        acc[MAXP + MAXT + e] += w * __shfl(w, src);
-      }
+  for (int ct = 0; ct < 4; ct++) {
+    const int gp = ct * PT + cl / pR;       // problem of the lane's column
+    const bool valid = cl < PT * pR && gp < ng;
+    base[ct] = slab_index(r, col0 + (valid ? (int64_t)ct * PT * pR + cl : 0), J.C, J.n_pad);
   }
-  // reduce over the 4 row phases of the wave, then over waves (fixed order)
+  const size_t ostride = (size_t)(J.C / 16) * 128;  // one row octet of a slab
+  const double* __restrict__ W = J.W;
+  auto loadA = [&](int ct, int64_t o) __attribute__((always_inline)) -> d2 {
+    return *reinterpret_cast<const d2*>(W + base[ct] + (size_t)o * ostride);
+  };
+  d4 acc[4][ET + 1];
+  mfma_dots<ET, true>(loadA, J.F, ldf, (J.n + 7) / 8, wave, lane, acc);
 #pragma unroll
-  for (int e = 0; e < MAXP + MAXT + 16; e++) {
-    double v = acc[e];
-    v += __shfl_xor(v, 16);
-    v += __shfl_xor(v, 32);
-    acc[e] = v;
-  }
-  if (rg == 0) {
-#pragma unroll
-    for (int e = 0; e < MAXP + MAXT; e++)
-      if (e < ldf) red[wave][cl][e] = acc[e];
-#pragma unroll
-    for (int e = 0; e < 16; e++)
-      if (e < pR) red[wave][cl][ldf + e] = acc[MAXP + MAXT + e];
-  }
-  __syncthreads();
-  // assemble S_i and c_i for the ng problems (Fig. 1)
-  for (int idx = threadIdx.x; idx < ng * p * p; idx += 64 * AS_WAVES) {
-    const int g = idx / (p * p), a = (idx % (p * p)) % p, b = (idx % (p * p)) / p;
-    double v;
-    if (a < pL && b < pL) {
-      v = J.STL[a + b * pL];
-    } else if (a >= pL && b >= pL) {
-      const int c = g * pR + (a - pL);
-      v = 0.0;
-      for (int w = 0; w < AS_WAVES; w++) v += red[w][c][ldf + (b - pL)];
-    } else {
-      const int qa = a >= pL ? a - pL : b - pL;   // genotype column of the problem
-      const int l = a >= pL ? b : a;              // fixed column
-      const int c = g * pR + qa;
-      v = 0.0;
-      for (int w = 0; w < AS_WAVES; w++) v += red[w][c][l];
-    }
-    Ssh[g][a + b * p] = v;
-  }
-  for (int idx = threadIdx.x; idx < ng * p * t; idx += 64 * AS_WAVES) {
-    const int g = idx / (p * t), a = (idx % (p * t)) % p, j = (idx % (p * t)) / p;
-    double v;
-    if (a < pL) {
-      v = J.CT[a + j * pL];
-    } else {
-      const int c = g * pR + (a - pL);
-      v = 0.0;
-      for (int w = 0; w < AS_WAVES; w++) v += red[w][c][pL + j];
-    }
-    Csh[g][a + j * p] = v;
-  }
-  __syncthreads();
+  for (int et = 0; et < ET; et++) reduce_slice<ET>(acc, et, wave, lane, red, dots, ldf, 0, 0);
+  reduce_slice<ET>(acc, ET, wave, lane, red, dots, 0, ldf, pR);
 
   // one wavefront per problem
   for (int g = wave; g < ng; g += AS_WAVES) {
+    const int c0 = 16 * (g / PT) + (g % PT) * pR;   // the problem's first column in dots
+    // S^(0)[a][b] of Fig. 1 from S_TL and the reduced dot products
+    auto S0 = [&](int a, int b) -> double {
+      if (a < pL && b < pL) return J.STL[a + b * pL];
+      if (a >= pL && b >= pL) return dots[c0 + a - pL][ldf + b - pL];
+      if (a >= pL) return dots[c0 + a - pL][b];
+      return dots[c0 + b - pL][a];
+    };
     double col[MAXP], crow[MAXT];
 #pragma unroll
-    for (int a = 0; a < MAXP; a++) col[a] = (lane < p && a < p) ? Ssh[g][a + lane * p] : 0.0;
+    for (int a = 0; a < MAXP; a++) col[a] = (lane < p && a < p) ? S0(a, lane) : 0.0;
 #pragma unroll
-    for (int j = 0; j < MAXT; j++) crow[j] = (lane < p && j < t) ? Csh[g][lane + j * p] : 0.0;
+    for (int j = 0; j < MAXT; j++) {
+      crow[j] = 0.0;
+      if (lane < p && j < t) crow[j] = lane < pL ? J.CT[lane + j * pL] : dots[c0 + lane - pL][pL + j];
+    }
     int fail = 0;
     wave_cholesky(col, p, lane, fail);
     if (!fail) {
@@ -787,10 +852,10 @@ __global__ __launch_bounds__(64 * AS_WAVES) void k_assemble_solve(const AsmTable
       if (REFINE) {
         // residual of the normal equations with the FP64-exact blocks
         const int64_t cbase = col0 + (int64_t)g * pR;  // first genotype column of the problem
-        double r[MAXT];
+        double rr[MAXT];
 #pragma unroll
         for (int j = 0; j < MAXT; j++) {
-          r[j] = 0.0;
+          rr[j] = 0.0;
           if (j < t) {
             double v = 0.0;
             if (lane < pL) v = J.CT[lane + j * pL];
@@ -801,15 +866,15 @@ __global__ __launch_bounds__(64 * AS_WAVES) void k_assemble_solve(const AsmTable
               if (lane < pL && b < pL) sab = J.STL[lane + b * pL];
               else if (lane < pL && b < p) sab = J.XZ[(cbase + b - pL) * ldf + lane];
               else if (lane < p && b < pL) sab = J.XZ[(cbase + lane - pL) * ldf + b];
-              else if (lane < p && b < p) sab = Ssh[g][lane + b * p];
+              else if (lane < p && b < p) sab = dots[c0 + lane - pL][ldf + b - pL];
               v -= sab * bb;
             }
-            r[j] = lane < p ? v : 0.0;
+            rr[j] = lane < p ? v : 0.0;
           }
         }
-        wave_cholsolve(col, r, p, t, lane);
+        wave_cholsolve(col, rr, p, t, lane);
 #pragma unroll
-        for (int j = 0; j < MAXT; j++) crow[j] += r[j];
+        for (int j = 0; j < MAXT; j++) crow[j] += rr[j];
         // undo the centering: b_L[icol] -= sum_q s_q b'_R[q]
 #pragma unroll
         for (int j = 0; j < MAXT; j++) {
@@ -837,70 +902,85 @@ __global__ __launch_bounds__(64 * AS_WAVES) void k_assemble_solve(const AsmTable
 // Centering pre-pass: per genotype column the exact dyadic shift
 // s = round(256 * mean(x)) / 256 (x - s is exact in FP32: at most 10
 // significant bits) and (x - s)^T Z with Z = M^{-1}[X_L | Y].
+// One work-group per 64 columns.  First pass: lane c sums column c over the
+// row octets w, w + 8, ... of its wave (one 8-byte load when the column
+// start and the leading dimension allow it, byte loads otherwise and in the
+// tail).  Second pass: (x - s)^T Z as the assembly's products on FP64 MFMA,
+// the A operand built from two genotype bytes per lane and tile.
+__device__ __forceinline__ void xz_octet(const int8_t* __restrict__ x, int64_t o, int64_t n,
+                                         bool vec, int8_t (&b)[8]) {
+  const int64_t r0 = 8 * o;
+  if (vec && r0 + 8 <= n) {
+    const int2 v = *reinterpret_cast<const int2*>(x + r0);
+    __builtin_memcpy(b, &v, 8);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 8; i++) b[i] = r0 + i < n ? x[r0 + i] : (int8_t)0;
+  }
+}
+
+template <int ET>
 __global__ __launch_bounds__(64 * AS_WAVES) void k_xz_shift(const XzTable tab) {
-  __shared__ int isum[AS_WAVES][16];
-  __shared__ double sh[16];
-  __shared__ double red[AS_WAVES][16][MAXP + MAXT];
+  __shared__ int isum[AS_WAVES][AS_COLS];
+  __shared__ double sh[AS_COLS];
+  __shared__ double red[AS_WAVES][AS_COLS][17];
+  __shared__ double dots[AS_COLS][AS_DOTS];
   int jb = 0;
   while (jb + 1 < tab.njobs && (int64_t)blockIdx.x >= tab.j[jb + 1].grp0) jb++;
   const XzDesc& J = tab.j[jb];
-  const int64_t col0 = ((int64_t)blockIdx.x - J.grp0) * 16;
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const int rg = lane / 16, cl = lane % 16;
-  const bool valid = col0 + cl < J.ncols;
-  const int64_t col = valid ? col0 + cl : col0;
-  const int8_t* __restrict__ x = J.X + col * J.ldx;
-  const int64_t nsteps = (J.n + 3) / 4;
-  int s = 0;
-  for (int64_t st = wave; st < nsteps; st += AS_WAVES) {
-    const int64_t row = 4 * st + rg;
-    if (valid && row < J.n) s += x[row];
+  const int64_t col0 = ((int64_t)blockIdx.x - J.grp0) * AS_COLS;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+  const int lane = threadIdx.x % 64;
+  const int64_t n = J.n, noct = (n + 7) / 8;
+  {
+    const bool valid = col0 + lane < J.ncols;
+    const int8_t* __restrict__ x = J.X + (valid ? col0 + lane : col0) * J.ldx;
+    const bool vec = (reinterpret_cast<uintptr_t>(J.X) % 8 == 0) && (J.ldx % 8 == 0);
+    int s = 0;
+    for (int64_t o0 = wave; o0 < noct; o0 += 8 * 4) {
+      int8_t b[4][8];
+#pragma unroll
+      for (int st = 0; st < 4; st++)
+        xz_octet(x, o0 + 8 * st < noct ? o0 + 8 * st : noct, n, vec, b[st]);
+#pragma unroll
+      for (int st = 0; st < 4; st++)
+#pragma unroll
+        for (int i = 0; i < 8; i++) s += b[st][i];
+    }
+    isum[wave][lane] = s;
   }
-  s += __shfl_xor(s, 16);
-  s += __shfl_xor(s, 32);
-  if (rg == 0) isum[wave][cl] = s;
   __syncthreads();
-  if (threadIdx.x < 16) {
+  if (threadIdx.x < AS_COLS) {
     int tot = 0;
     for (int w = 0; w < AS_WAVES; w++) tot += isum[w][threadIdx.x];
-    const double shift = rint(256.0 * (double)tot / (double)J.n) / 256.0;
+    const double shift = rint(256.0 * (double)tot / (double)n) / 256.0;
     sh[threadIdx.x] = shift;
     if (col0 + threadIdx.x < J.ncols) J.shift[col0 + threadIdx.x] = shift;
   }
   __syncthreads();
-  const double sft = sh[cl];
+  const int r = lane / 16, cl = lane % 16;
+  const int8_t* xs[4];
+  double sft[4];
+#pragma unroll
+  for (int ct = 0; ct < 4; ct++) {
+    const int64_t c = col0 + 16 * ct + cl;
+    xs[ct] = J.X + (c < J.ncols ? c : col0) * J.ldx;
+    sft[ct] = sh[16 * ct + cl];
+  }
+  auto loadA = [&](int ct, int64_t o) __attribute__((always_inline)) -> d2 {
+    const int64_t r0 = 8 * o + r, r1 = r0 + 4;
+    const double a0 = r0 < n ? (double)xs[ct][r0] - sft[ct] : 0.0;
+    const double a1 = r1 < n ? (double)xs[ct][r1] - sft[ct] : 0.0;
+    return d2{a0, a1};
+  };
   const int ldf = J.ldf;
-  double acc[MAXP + MAXT];
+  d4 acc[4][ET + 1];
+  mfma_dots<ET, false>(loadA, J.Z, ldf, noct, wave, lane, acc);
 #pragma unroll
-  for (int e = 0; e < MAXP + MAXT; e++) acc[e] = 0.0;
-  for (int64_t st = wave; st < nsteps; st += AS_WAVES) {
-    const int64_t row = 4 * st + rg;
-    const double xv = (valid && row < J.n) ? (double)x[row] - sft : 0.0;
-    const double* __restrict__ z = J.Z + row * ldf;
-#pragma unroll
-    for (int e = 0; e < MAXP + MAXT; e++)
-      if (e < ldf) acc[e] += xv * z[e];
-  }
-#pragma unroll
-  for (int e = 0; e < MAXP + MAXT; e++) {
-    double v = acc[e];
-    v += __shfl_xor(v, 16);
-    v += __shfl_xor(v, 32);
-    acc[e] = v;
-  }
-  if (rg == 0) {
-#pragma unroll
-    for (int e = 0; e < MAXP + MAXT; e++)
-      if (e < ldf) red[wave][cl][e] = acc[e];
-  }
-  __syncthreads();
-  for (int idx = threadIdx.x; idx < 16 * ldf; idx += 64 * AS_WAVES) {
+  for (int et = 0; et < ET; et++) reduce_slice<ET>(acc, et, wave, lane, red, dots, ldf, 0, 0);
+  for (int idx = threadIdx.x; idx < AS_COLS * ldf; idx += 64 * AS_WAVES) {
     const int c = idx / ldf, e = idx % ldf;
-    if (col0 + c < J.ncols) {
-      double v = 0.0;
-      for (int w = 0; w < AS_WAVES; w++) v += red[w][c][e];
-      J.XZ[(col0 + c) * ldf + e] = v;
-    }
+    if (col0 + c < J.ncols) J.XZ[(col0 + c) * ldf + e] = dots[c][e];
   }
 }
 
@@ -1170,8 +1250,16 @@ hipError_t launch_gram(const double* F, int64_t n, int pL, int t, double* STL, d
 }
 
 hipError_t launch_assemble_solve(const AsmTable& tab, int64_t ngroups, bool refine, hipStream_t st) {
-  if (refine) k_assemble_solve<true><<<(unsigned)ngroups, 64 * AS_WAVES, 0, st>>>(tab);
-  else k_assemble_solve<false><<<(unsigned)ngroups, 64 * AS_WAVES, 0, st>>>(tab);
+  int w = 1;  // widest F = [W_L | ytil] of the table: one or two 16-column tiles
+  for (int i = 0; i < tab.njobs; i++) w = std::max(w, tab.j[i].pL + tab.j[i].t);
+  const unsigned g = (unsigned)ngroups, nt = 64 * AS_WAVES;
+  if (w <= 16) {
+    if (refine) k_assemble_solve<true, 1><<<g, nt, 0, st>>>(tab);
+    else k_assemble_solve<false, 1><<<g, nt, 0, st>>>(tab);
+  } else {
+    if (refine) k_assemble_solve<true, 2><<<g, nt, 0, st>>>(tab);
+    else k_assemble_solve<false, 2><<<g, nt, 0, st>>>(tab);
+  }
   return hipGetLastError();
 }
 
@@ -1185,7 +1273,11 @@ hipError_t launch_trsm_mixed(const JobTable& tab, int64_t nslabs, int C, hipStre
 }
 
 hipError_t launch_xz_shift(const XzTable& tab, int64_t ngroups, hipStream_t st) {
-  k_xz_shift<<<(unsigned)ngroups, 64 * AS_WAVES, 0, st>>>(tab);
+  int w = 1;
+  for (int i = 0; i < tab.njobs; i++) w = std::max(w, tab.j[i].ldf);
+  const unsigned g = (unsigned)ngroups, nt = 64 * AS_WAVES;
+  if (w <= 16) k_xz_shift<1><<<g, nt, 0, st>>>(tab);
+  else k_xz_shift<2><<<g, nt, 0, st>>>(tab);
   return hipGetLastError();
 }
 
