@@ -77,15 +77,14 @@ def measured_traffic(batch, slab_cols, precision):
     """HBM bytes per launch of the FP64 triangular-solve kernel from the
     committed rocprofv3 counter summary, or None if the kernel source has
     changed since the counters were taken (or the launch shape differs)."""
-    import hashlib
+    from paper_1210_7325_amd.build import trsm_source_digest
     if precision != "fp64":
         return None
     path = os.path.join(ROOT, "profiles", "trsm_fp64_n10000_traffic.md")
-    src = os.path.join(ROOT, "paper_1210_7325_amd", "csrc", "gls_kernels.hip")
     try:
         kv = dict(l.split(": ", 1) for l in open(path).read().splitlines() if ": " in l)
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-        if kv.get("kernel_source_sha256") != sha or int(kv["blocks_per_launch"]) != batch \
+        if kv.get("kernel_source_sha256") != trsm_source_digest() \
+                or int(kv["blocks_per_launch"]) != batch \
                 or slab_cols != 64:
             return None
         return float(kv["traffic_bytes_per_launch"])

@@ -40,13 +40,36 @@ def _run(cmd):
     return out
 
 
+# translation units of libgls.so, one per step of the path (plus the C ABI)
+GLS_UNITS = ("gls_factor.hip", "gls_fixed.hip", "gls_trsm.hip", "gls_trsm_mixed.hip",
+             "gls_assemble.hip", "gls_api.cpp")
+
+
+def trsm_source_digest() -> str:
+    """SHA-256 over everything that decides the FP64 triangular-solve
+    kernel's machine code: its source, the shared device headers and the
+    compiler flags.  Counter readings taken for one digest are stale for
+    any other."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("gls_trsm.hip", "gls_device.h", "gls_internal.h"):
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(f.read())
+    h.update(" ".join(HIP_FLAGS[:-2]).encode())  # flags without the include paths
+    return h.hexdigest()
+
+
 def build_gls(verbose: bool = False) -> str:
+    from concurrent.futures import ThreadPoolExecutor
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
-    for src, lang in (("gls_kernels.hip", "hip"), ("gls_api.cpp", "hip")):
+
+    def compile_unit(src):
         obj = os.path.join(BUILD, src + ".o")
-        _run([HIPCC, "-x", lang, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
-        objs.append(obj)
+        _run([HIPCC, "-x", "hip", *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
+        return obj
+
+    with ThreadPoolExecutor(max_workers=min(len(GLS_UNITS), os.cpu_count() or 1)) as ex:
+        objs = list(ex.map(compile_unit, GLS_UNITS))
     tmp = os.path.join(PKG, "libgls.so.tmp")
     _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp])
     os.replace(tmp, os.path.join(PKG, "libgls.so"))

@@ -1,0 +1,74 @@
+// Device-side helpers and data layouts shared by the solver's kernels
+// (gfx950 / CDNA4).
+//
+// Paper: Fabregat-Traver, Aulchenko, Bientinesi, "Solving Sequences of
+// Generalized Least-Squares Problems on Multi-threaded Architectures".
+// The kernels implement the steps of the in-core algorithm "hp-gwas"
+// (Sec. 2, Alg. 5): potrf of M, trsm of X_L / y / the genotype block,
+// syrk/gemv for S_TL and C_T, and per problem the gemv/dot assembly of
+// S_i, c_i (Fig. 1) followed by posv.
+//
+// Layouts (all FP64 unless noted):
+//  * A: the factorization's work matrix, n_pad x n_pad column-major
+//    (n_pad = K*NB), identity on the padded diagonal.
+//  * Packed factor for the triangular solve ("fragment layout"): the strip
+//    of row block k, L[kNB:(k+1)NB, 0:kNB], is stored as a sequence of
+//    k-step pairs; one pair holds, for each 16-row tile, 64 lanes x 2
+//    doubles, lane l of k-step s holding L[row0 + l%16][4s + l/16] (the A
+//    operand of v_mfma_f64_16x16x4f64).  Strip k starts at k(k-1)/2 NB^2.
+//    The inverted diagonal blocks use the same layout with NB columns.
+//  * Whitened genotypes ("slab layout"): columns are grouped in slabs of C;
+//    a slab holds n_pad x C values as k-step pairs of 16-column tiles, lane
+//    l of k-step s holding W[4s + l/16][16ct + l%16] (the B operand).
+//  * FP64 MFMA output: lane l, element i holds D[l/16 + 4i][l%16], which is
+//    exactly the B-operand position of k-step (tile_row0/4 + i) at lane l,
+//    so results go to the slab layout without any lane exchange.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <math.h>
+
+#include <algorithm>
+
+#include "gls_internal.h"
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+#define MFMA64(a, b, c) __builtin_amdgcn_mfma_f64_16x16x4f64((a), (b), (c), 0, 0, 0)
+#define MFMA32(a, b, c) __builtin_amdgcn_mfma_f32_16x16x4f32((a), (b), (c), 0, 0, 0)
+
+namespace gls {
+
+
+// ---------------------------------------------------------------------------
+// small helpers
+__device__ __forceinline__ double bcast_lane(double v, int src) {
+  // v of lane `src` to every lane (src is wave-uniform)
+  int2 x = *reinterpret_cast<int2*>(&v);
+  x.x = __builtin_amdgcn_readlane(x.x, src);
+  x.y = __builtin_amdgcn_readlane(x.y, src);
+  return *reinterpret_cast<double*>(&x);
+}
+
+__device__ __forceinline__ size_t strip_offset(int k) {
+  return (size_t)k * (size_t)(k - 1) / 2 * (size_t)(NB * NB);
+}
+
+// Address of W(row, col) in the slab layout.
+__device__ __forceinline__ size_t slab_index(int64_t row, int64_t col, int C, int64_t n_pad) {
+  const int64_t slab = col / C, cc = col % C;
+  const int64_t ks = row / 4;
+  return (size_t)slab * n_pad * C + ((size_t)(ks / 2) * (C / 16) + cc / 16) * 128 +
+         (size_t)(((row % 4) * 16 + cc % 16) * 2 + (ks % 2));
+}
+
+
+template <typename TIn>
+__device__ __forceinline__ double load_x(const TIn* __restrict__ X, int64_t ldx, int64_t row,
+                                         int64_t col, int64_t n, int64_t ncols) {
+  return (row < n && col < ncols) ? (double)X[col * ldx + row] : 0.0;
+}
+
+}  // namespace gls

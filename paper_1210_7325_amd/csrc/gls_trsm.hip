@@ -1,0 +1,188 @@
+// FP64 blocked triangular solve of genotype blocks (a2), the hot kernel.
+#include "gls_device.h"
+
+namespace gls {
+
+// ---------------------------------------------------------------------------
+// a1/a2: blocked lower triangular solve  W = L^{-1} X  (the trsm of Alg. 5,
+// grouped over many right-hand sides as the paper prescribes)
+//
+// One work-group owns a slab of C columns and walks the row blocks
+// k = 0..K-1 (left-looking):
+//   R_k = X_k - sum_{j<k} L_kj W_j     FP64 MFMA, operands streamed from the
+//                                      packed strip and the slab's own W
+//   W_k = inv(L_kk) R_k                FP64 MFMA, R_k staged in LDS
+// The waves split the NB rows of a block (WR ways) and the C columns (WC
+// ways).  X is int8 genotypes (exact in FP64) or FP64 (fixed part).
+template <int C, int WR, int WC, int D, typename TIn>
+__global__ __launch_bounds__(64 * WR * WC) void k_trsm(const JobTable tab) {
+  constexpr int RW = NB / WR, RT = RW / 16;
+  constexpr int CW = C / WC, CT = CW / 16;
+  constexpr int CTS = C / 16;  // column tiles per slab
+  constexpr int NPB = NB / 8;  // k-step pairs per row block
+  static_assert(RT >= 1 && CT >= 1, "tile shape");
+  static_assert(NPB % D == 0, "prefetch depth must divide the pairs of a block");
+  __shared__ __attribute__((aligned(16))) double Rl[NB * C];
+
+  // find the job of this slab
+  int jb = 0;
+  while (jb + 1 < tab.njobs && (int64_t)blockIdx.x >= tab.j[jb + 1].slab0) jb++;
+  const JobDesc& J = tab.j[jb];
+  const int64_t slab = (int64_t)blockIdx.x - J.slab0;
+  const int K = J.K;
+  const int64_t n = J.n, ncols = J.ncols;
+  const TIn* __restrict__ X = reinterpret_cast<const TIn*>(J.X);
+  const int64_t ldx = J.ldx;
+  const double* __restrict__ Lstrips = J.Lstrips;
+  const double* __restrict__ LinvP = J.LinvP;
+  double* __restrict__ Wslab = J.W + slab * (int64_t)K * NB * C;
+
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int wr = wave / WC, wc = wave % WC;
+  const int64_t col_base = slab * C + wc * CW;
+
+  for (int k = 0; k < K; k++) {
+    // this block's right-hand side, loaded early (consumed after the GEMM)
+    double xv[RT][CT][4];
+#pragma unroll
+    for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+      for (int ct = 0; ct < CT; ct++)
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+          xv[rt][ct][i] = load_x<TIn>(X, ldx, (int64_t)k * NB + wr * RW + rt * 16 + lane / 16 + 4 * i,
+                                      col_base + ct * 16 + lane % 16, n, ncols);
+
+    d4 acc[RT][CT];
+#pragma unroll
+    for (int a = 0; a < RT; a++)
+#pragma unroll
+      for (int b = 0; b < CT; b++) acc[a][b] = (d4){0, 0, 0, 0};
+
+    // sum_{j<k} L_kj W_j: software pipeline with D k-step pairs in flight
+    const double* __restrict__ Ls = Lstrips + strip_offset(k) + (size_t)(wr * RT) * 128 + lane * 2;
+    const double* __restrict__ Wb = Wslab + (size_t)(wc * CT) * 128 + lane * 2;
+    const int npairs = k * NPB;
+    if (npairs > 0) {
+      d2 a[D][RT], b[D][CT];
+#pragma unroll
+      for (int s = 0; s < D; s++) {
+#pragma unroll
+        for (int rt = 0; rt < RT; rt++)
+          a[s][rt] = *reinterpret_cast<const d2*>(Ls + ((size_t)s * (NB / 16) + rt) * 128);
+#pragma unroll
+        for (int ct = 0; ct < CT; ct++)
+          b[s][ct] = *reinterpret_cast<const d2*>(Wb + ((size_t)s * CTS + ct) * 128);
+      }
+      for (int kp0 = 0; kp0 < npairs; kp0 += D) {
+#pragma unroll
+        for (int s = 0; s < D; s++) {
+#pragma unroll
+          for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+            for (int ct = 0; ct < CT; ct++) {
+              acc[rt][ct] = MFMA64(a[s][rt].x, b[s][ct].x, acc[rt][ct]);
+              acc[rt][ct] = MFMA64(a[s][rt].y, b[s][ct].y, acc[rt][ct]);
+            }
+          // refill this stage with pair kp0 + s + D (clamped to the last
+          // pair; the clamped tail loads are never used)
+          int nx = kp0 + s + D;
+          nx = nx < npairs ? nx : npairs - 1;
+#pragma unroll
+          for (int rt = 0; rt < RT; rt++)
+            a[s][rt] = *reinterpret_cast<const d2*>(Ls + ((size_t)nx * (NB / 16) + rt) * 128);
+#pragma unroll
+          for (int ct = 0; ct < CT; ct++)
+            b[s][ct] = *reinterpret_cast<const d2*>(Wb + ((size_t)nx * CTS + ct) * 128);
+          // keep the refill loads issued here, D stages ahead of their use
+          asm volatile("" ::: "memory");
+        }
+      }
+    }
+
+    // R_k = X_k - acc, staged in LDS in the B-operand pair layout
+#pragma unroll
+    for (int rt = 0; rt < RT; rt++) {
+      const int rowl = wr * RW + rt * 16;  // row of the tile within the block
+#pragma unroll
+      for (int ct = 0; ct < CT; ct++) {
+#pragma unroll
+        for (int i = 0; i < 4; i += 2) {
+          const int kp = (rowl / 4 + i) / 2;
+          *reinterpret_cast<d2*>(&Rl[((size_t)kp * CTS + wc * CT + ct) * 128 + lane * 2]) =
+              (d2){xv[rt][ct][i] - acc[rt][ct][i], xv[rt][ct][i + 1] - acc[rt][ct][i + 1]};
+        }
+      }
+    }
+    __syncthreads();
+
+    // W_k = inv(L_kk) R_k ; inv(L_kk) is lower triangular, so the k-steps
+    // beyond this wave's last row are zero and skipped
+#pragma unroll
+    for (int a = 0; a < RT; a++)
+#pragma unroll
+      for (int b = 0; b < CT; b++) acc[a][b] = (d4){0, 0, 0, 0};
+    const double* __restrict__ Li = LinvP + (size_t)k * NB * NB + (size_t)(wr * RT) * 128 + lane * 2;
+    const int kp_end = (wr * RW + RW) / 8;
+    for (int kp = 0; kp < kp_end; kp++) {
+      d2 a[RT], b[CT];
+#pragma unroll
+      for (int rt = 0; rt < RT; rt++)
+        a[rt] = *reinterpret_cast<const d2*>(Li + ((size_t)kp * (NB / 16) + rt) * 128);
+#pragma unroll
+      for (int ct = 0; ct < CT; ct++)
+        b[ct] = *reinterpret_cast<const d2*>(&Rl[((size_t)kp * CTS + wc * CT + ct) * 128 + lane * 2]);
+#pragma unroll
+      for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+        for (int ct = 0; ct < CT; ct++) {
+          acc[rt][ct] = MFMA64(a[rt].x, b[ct].x, acc[rt][ct]);
+          acc[rt][ct] = MFMA64(a[rt].y, b[ct].y, acc[rt][ct]);
+        }
+    }
+    // store W_k (slab layout): element i of the FP64 output is k-step
+    // (row0/4 + i) at the same lane
+#pragma unroll
+    for (int rt = 0; rt < RT; rt++) {
+      const int64_t ks0 = (int64_t)k * (NB / 4) + (wr * RW + rt * 16) / 4;
+#pragma unroll
+      for (int ct = 0; ct < CT; ct++)
+#pragma unroll
+        for (int i = 0; i < 4; i += 2)
+          *reinterpret_cast<d2*>(Wslab + ((size_t)((ks0 + i) / 2) * CTS + wc * CT + ct) * 128 + lane * 2) =
+              (d2){acc[rt][ct][i], acc[rt][ct][i + 1]};
+    }
+    __threadfence_block();
+    __syncthreads();
+  }
+}
+
+// Slab layout -> caller's column-major array (inspection).
+__global__ void k_slab_to_colmajor(const double* __restrict__ W, int C, int64_t n_pad, int64_t n,
+                                   int64_t col0, int64_t ncols, double* __restrict__ out, int64_t ldo) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t c = blockIdx.y; c < ncols; c += gridDim.y) {
+    if (r >= n) return;
+    out[r + c * ldo] = W[slab_index(r, col0 + c, C, n_pad)];
+  }
+}
+
+
+hipError_t launch_trsm_i8(const JobTable& tab, int64_t nslabs, int C, hipStream_t st) {
+  switch (C) {
+    case 16: k_trsm<16, 4, 1, TRSM_DEPTH, int8_t><<<(unsigned)nslabs, 256, 0, st>>>(tab); break;
+    case 32: k_trsm<32, 4, 2, TRSM_DEPTH, int8_t><<<(unsigned)nslabs, 512, 0, st>>>(tab); break;
+    case 64: k_trsm<64, 4, 2, TRSM_DEPTH, int8_t><<<(unsigned)nslabs, 512, 0, st>>>(tab); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_slab_to_colmajor(const double* W, int C, int64_t n_pad, int64_t n, int64_t col0,
+                                   int64_t ncols, double* out, int64_t ldo, hipStream_t st) {
+  dim3 grid((unsigned)((n + 255) / 256), (unsigned)(ncols < 65535 ? ncols : 65535));
+  k_slab_to_colmajor<<<grid, 256, 0, st>>>(W, C, n_pad, n, col0, ncols, out, ldo);
+  return hipGetLastError();
+}
+
+}  // namespace gls

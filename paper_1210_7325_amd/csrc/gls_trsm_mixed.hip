@@ -1,0 +1,196 @@
+// Mixed-precision triangular solve of the FP32_REFINE form (a5).
+#include "gls_device.h"
+
+namespace gls {
+
+// Mixed-precision blocked lower solve W = L^{-1}(X - 1 s^T): as k_trsm, but
+// each off-diagonal product L_kj W_j uses FP32-rounded operands on FP32 MFMA
+// (v_mfma_f32_16x16x4f32) with FP32 accumulation over one chunk of CHQ
+// k-step quads (4 k-steps each; CHQ = NB/16 is one whole diagonal block),
+// and the chunk is added into an FP64 running accumulator.  The diagonal
+// step inv(L_kk) R_k stays FP64.  Both W (FP64, for the assembly) and an
+// FP32 copy (quad layout, for later trailing products) are stored.
+// The FP32 output layout is lane l, element i -> row 4(l/16) + i.
+template <int C, int WR, int WC, int D, int CHQ>
+__global__ __launch_bounds__(64 * WR * WC) void k_trsm_mixed(const JobTable tab) {
+  constexpr int RW = NB / WR, RT = RW / 16;
+  constexpr int CW = C / WC, CT = CW / 16;
+  constexpr int CTS = C / 16;
+  constexpr int NQB = NB / 16;  // k-step quads per row block
+  static_assert(NQB % CHQ == 0 && (CHQ % D == 0 || D % CHQ == 0), "chunking");
+  __shared__ __attribute__((aligned(16))) double Rl[NB * C];
+
+  int jb = 0;
+  while (jb + 1 < tab.njobs && (int64_t)blockIdx.x >= tab.j[jb + 1].slab0) jb++;
+  const JobDesc& J = tab.j[jb];
+  const int64_t slab = (int64_t)blockIdx.x - J.slab0;
+  const int K = J.K;
+  const int64_t n = J.n, ncols = J.ncols;
+  const int8_t* __restrict__ X = reinterpret_cast<const int8_t*>(J.X);
+  const int64_t ldx = J.ldx;
+  const double* __restrict__ shift = J.shift;
+  const float* __restrict__ L32 = J.Lstrips32;
+  const double* __restrict__ LinvP = J.LinvP;
+  double* __restrict__ Wslab = J.W + slab * (int64_t)K * NB * C;
+  float* __restrict__ W32slab = J.W32 + slab * (int64_t)K * NB * C;
+
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int wr = wave / WC, wc = wave % WC;
+  const int64_t col_base = slab * C + wc * CW;
+
+  for (int k = 0; k < K; k++) {
+    double xv[RT][CT][4];
+#pragma unroll
+    for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+      for (int ct = 0; ct < CT; ct++) {
+        const int64_t col = col_base + ct * 16 + lane % 16;
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+          const int64_t row = (int64_t)k * NB + wr * RW + rt * 16 + 4 * (lane / 16) + i;
+          xv[rt][ct][i] = (row < n && col < ncols) ? (double)X[col * ldx + row] - shift[col] : 0.0;
+        }
+      }
+
+    d4 acc[RT][CT];
+    f4 c32[RT][CT];
+#pragma unroll
+    for (int a = 0; a < RT; a++)
+#pragma unroll
+      for (int b = 0; b < CT; b++) {
+        acc[a][b] = (d4){0, 0, 0, 0};
+        c32[a][b] = (f4){0, 0, 0, 0};
+      }
+
+    const float* __restrict__ Ls = L32 + strip_offset(k) + (size_t)(wr * RT) * 256 + lane * 4;
+    const float* __restrict__ Wb = W32slab + (size_t)(wc * CT) * 256 + lane * 4;
+    const int nq = k * NQB;
+    if (nq > 0) {
+      f4 a[D][RT], b[D][CT];
+#pragma unroll
+      for (int s = 0; s < D; s++) {
+#pragma unroll
+        for (int rt = 0; rt < RT; rt++)
+          a[s][rt] = *reinterpret_cast<const f4*>(Ls + ((size_t)s * (NB / 16) + rt) * 256);
+#pragma unroll
+        for (int ct = 0; ct < CT; ct++)
+          b[s][ct] = *reinterpret_cast<const f4*>(Wb + ((size_t)s * CTS + ct) * 256);
+      }
+      for (int q0 = 0; q0 < nq; q0 += D) {
+#pragma unroll
+        for (int s = 0; s < D; s++) {
+#pragma unroll
+          for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+            for (int ct = 0; ct < CT; ct++) {
+              c32[rt][ct] = MFMA32(a[s][rt].x, b[s][ct].x, c32[rt][ct]);
+              c32[rt][ct] = MFMA32(a[s][rt].y, b[s][ct].y, c32[rt][ct]);
+              c32[rt][ct] = MFMA32(a[s][rt].z, b[s][ct].z, c32[rt][ct]);
+              c32[rt][ct] = MFMA32(a[s][rt].w, b[s][ct].w, c32[rt][ct]);
+            }
+          int nx = q0 + s + D;
+          nx = nx < nq ? nx : nq - 1;
+#pragma unroll
+          for (int rt = 0; rt < RT; rt++)
+            a[s][rt] = *reinterpret_cast<const f4*>(Ls + ((size_t)nx * (NB / 16) + rt) * 256);
+#pragma unroll
+          for (int ct = 0; ct < CT; ct++)
+            b[s][ct] = *reinterpret_cast<const f4*>(Wb + ((size_t)nx * CTS + ct) * 256);
+          asm volatile("" ::: "memory");
+          if (CHQ <= D && (s + 1) % CHQ == 0) {
+            // end of an FP32 chunk: fold into the FP64 running sum
+#pragma unroll
+            for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+              for (int ct = 0; ct < CT; ct++) {
+#pragma unroll
+                for (int i = 0; i < 4; i++) acc[rt][ct][i] += (double)c32[rt][ct][i];
+                c32[rt][ct] = (f4){0, 0, 0, 0};
+              }
+          }
+        }
+        if (CHQ > D && (q0 + D) % CHQ == 0) {
+#pragma unroll
+          for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+            for (int ct = 0; ct < CT; ct++) {
+#pragma unroll
+              for (int i = 0; i < 4; i++) acc[rt][ct][i] += (double)c32[rt][ct][i];
+              c32[rt][ct] = (f4){0, 0, 0, 0};
+            }
+        }
+      }
+    }
+
+    // R_k = (x - s) - acc, to LDS in the FP64 B-operand pair layout: element
+    // (row 4g + i) of the FP32 output goes to k-step (row0/4 + g), lane 16i + l%16
+#pragma unroll
+    for (int rt = 0; rt < RT; rt++) {
+      const int rowl = wr * RW + rt * 16;
+      const int ks = rowl / 4 + lane / 16;
+#pragma unroll
+      for (int ct = 0; ct < CT; ct++)
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+          Rl[((size_t)(ks / 2) * CTS + wc * CT + ct) * 128 + (i * 16 + lane % 16) * 2 + (ks % 2)] =
+              xv[rt][ct][i] - acc[rt][ct][i];
+    }
+    __syncthreads();
+
+    d4 w64[RT][CT];
+#pragma unroll
+    for (int a = 0; a < RT; a++)
+#pragma unroll
+      for (int b = 0; b < CT; b++) w64[a][b] = (d4){0, 0, 0, 0};
+    const double* __restrict__ Li = LinvP + (size_t)k * NB * NB + (size_t)(wr * RT) * 128 + lane * 2;
+    const int kp_end = (wr * RW + RW) / 8;
+    for (int kp = 0; kp < kp_end; kp++) {
+      d2 a[RT], b[CT];
+#pragma unroll
+      for (int rt = 0; rt < RT; rt++)
+        a[rt] = *reinterpret_cast<const d2*>(Li + ((size_t)kp * (NB / 16) + rt) * 128);
+#pragma unroll
+      for (int ct = 0; ct < CT; ct++)
+        b[ct] = *reinterpret_cast<const d2*>(&Rl[((size_t)kp * CTS + wc * CT + ct) * 128 + lane * 2]);
+#pragma unroll
+      for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+        for (int ct = 0; ct < CT; ct++) {
+          w64[rt][ct] = MFMA64(a[rt].x, b[ct].x, w64[rt][ct]);
+          w64[rt][ct] = MFMA64(a[rt].y, b[ct].y, w64[rt][ct]);
+        }
+    }
+    // store W_k: FP64 pairs (identity per lane) and the FP32 quad copy
+    // (element i of the FP64 output is k-step row0/4 + i, i.e. position i of
+    // quad row0/16, same lane)
+#pragma unroll
+    for (int rt = 0; rt < RT; rt++) {
+      const int64_t row0 = (int64_t)k * NB + wr * RW + rt * 16;
+      const int64_t ks0 = row0 / 4;
+#pragma unroll
+      for (int ct = 0; ct < CT; ct++) {
+#pragma unroll
+        for (int i = 0; i < 4; i += 2)
+          *reinterpret_cast<d2*>(Wslab + ((size_t)((ks0 + i) / 2) * CTS + wc * CT + ct) * 128 + lane * 2) =
+              (d2){w64[rt][ct][i], w64[rt][ct][i + 1]};
+        *reinterpret_cast<f4*>(W32slab + ((size_t)(row0 / 16) * CTS + wc * CT + ct) * 256 + lane * 4) =
+            (f4){(float)w64[rt][ct][0], (float)w64[rt][ct][1], (float)w64[rt][ct][2],
+                 (float)w64[rt][ct][3]};
+      }
+    }
+    __threadfence_block();
+    __syncthreads();
+  }
+}
+
+
+hipError_t launch_trsm_mixed(const JobTable& tab, int64_t nslabs, int C, hipStream_t st) {
+  switch (C) {
+    case 32: k_trsm_mixed<32, 4, 2, 4, FP32_CHUNK_QUADS><<<(unsigned)nslabs, 512, 0, st>>>(tab); break;
+    case 64: k_trsm_mixed<64, 4, 2, 4, FP32_CHUNK_QUADS><<<(unsigned)nslabs, 512, 0, st>>>(tab); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace gls
