@@ -58,7 +58,8 @@ def problem(n, pL, pR, m, t=1, q=None, h=0.5, maf=(0.05, 0.5), seed=0):
 
 @pytest.mark.parametrize("n,pL,pR,t,m,block", [
     (1000, 3, 1, 1, 2000, 1024), (2000, 16, 4, 1, 300, 128), (129, 5, 1, 8, 90, 64),
-    (700, 3, 2, 2, 100, 100), (1500, 3, 1, 1, 500, 500),
+    (700, 3, 2, 2, 100, 100), (1500, 3, 1, 1, 500, 500), (600, 2, 5, 2, 60, 31),
+    (500, 3, 9, 3, 30, 16),
 ])
 def test_fp32_refine_parity(G, n, pL, pR, t, m, block):
     say("fp32 form", n, pL, pR, t, m)

@@ -129,6 +129,10 @@ def test_small_workload_parity(G):
 @pytest.mark.parametrize("n,pL,pR,t,m,block", [
     (63, 3, 1, 1, 37, 16), (64, 2, 2, 1, 20, 7), (65, 4, 3, 2, 33, 33), (129, 16, 4, 1, 50, 17),
     (200, 5, 1, 8, 70, 64), (300, 1, 1, 1, 5, 5), (1500, 3, 1, 1, 300, 256), (257, 19, 1, 3, 40, 40),
+    # genotype blocks wider than one column: problems per 16-column tile
+    # floor(16 / p_R) = 3, 2, 1, 1 (tiles left partly empty), two F tiles
+    (300, 2, 5, 2, 45, 19), (150, 3, 7, 3, 21, 10), (333, 10, 9, 8, 13, 13), (200, 1, 16, 1, 9, 4),
+    (401, 2, 3, 1, 150, 150),
 ])
 def test_ragged_shapes_parity(G, n, pL, pR, t, m, block):
     say("ragged", n, pL, pR, t, m, block)
