@@ -130,14 +130,23 @@ def upload_genotypes(torch, w, m):
 
 
 def run_step(gls, torch, dM, dXL, dY, dXR, w, m, block, streams, slab_cols, Bout, info,
-             timing=False, batch=4, precision="fp64"):
+             timing=False, batch=4, precision="fp64", phases=None):
     """One full pass: factor, whiten, all blocks.  `batch` blocks of `block`
     SNPs are whitened by one launch (gls_solve_multi over forked handles,
     each with its own workspace); launch groups rotate over `streams`.
-    Returns the kernel times recorded by each group's first handle."""
+    Returns the kernel times recorded by each group's first handle.  With
+    `phases` (a list), four events on the first stream are appended: start,
+    after the factorization, after the fixed part, after the last block."""
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)] if phases is not None else None
+    if ev:
+        ev[0].record(streams[0])
     c = gls.Cohort(dM, precision=precision, stream=streams[0])
+    if ev:
+        ev[1].record(streams[0])
     c.set_slab_cols(slab_cols)
     c.whiten_fixed(dXL, dY, intercept_col=0)
+    if ev:
+        ev[2].record(streams[0])
     groups = []
     for si, s in enumerate(streams):
         hs = [c if si == 0 and j == 0 else c.fork(s) for j in range(batch)]
@@ -157,6 +166,11 @@ def run_step(gls, torch, dM, dXL, dY, dXR, w, m, block, streams, slab_cols, Bout
     times = None
     if timing:
         times = [(hs[0].kernel_time(0), hs[0].kernel_time(1)) for _, hs in groups]
+    if ev:
+        for s in streams[1:]:
+            streams[0].wait_stream(s)
+        ev[3].record(streams[0])
+        phases.extend(ev)
     for s in streams:
         s.synchronize()
     for _, hs in groups:
@@ -176,12 +190,17 @@ def time_form(gls, torch, args, w, m, block, batch, dM, dXL, dY, dXR, Bout, info
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     kt = []
+    ph = []
     for i in range(args.steps):
         kt.append(run_step(gls, torch, dM, dXL, dY, dXR, w, m, block, streams, args.slab_cols,
-                           Bout, info, timing=True, batch=batch, precision=precision))
+                           Bout, info, timing=True, batch=batch, precision=precision,
+                           phases=ph if i == args.steps - 1 else None))
         log(f"[{precision}] step {i} done")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    # the last step split into factorization (a0), fixed part (a1) and the
+    # sequence of blocks (a2-a4), from events on the first stream
+    factor_ms, fixed_ms, solve_ms = (ph[j].elapsed_time(ph[j + 1]) for j in range(3))
     trsm_ms = sum(t[0][0] for step in kt for t in step)
     trsm_n = sum(t[0][1] for step in kt for t in step)
     asm_ms = sum(t[1][0] for step in kt for t in step)
@@ -197,6 +216,7 @@ def time_form(gls, torch, args, w, m, block, batch, dM, dXL, dY, dXR, Bout, info
         "flops_per_launch": flops_per_launch, "trsm_tflops": achieved, "peak": peak,
         "step_tflops": step_tflops, "assemble_avg_ms": asm_ms / max(asm_n, 1),
         "rank_deficient": int((info != 0).sum()),
+        "factor_ms": factor_ms, "fixed_ms": fixed_ms, "solve_ms": solve_ms,
     }
     log(f"[{precision}] {r['value']:.0f} b_i/s, {r['ms_per_step']:.1f} ms/step, TRSM "
         f"{achieved:.1f} TFLOP/s ({achieved / peak * 100:.1f}% of {peak}), step {step_tflops:.1f}")
@@ -246,11 +266,42 @@ def cpu_baseline(w, M, XL, Y, budget_s, lu=None, t_factor=None):
     t_sample = time.time() - t0
     per = t_sample / sample
     total = t_factor + per * w.m
-    return {
+    out = {
         "value": w.m / total, "unit": "b_i/s", "cores": int(cores), "kind": "oracle",
         "sample": (f"LU of M (n={w.n}) {t_factor:.1f}s + {sample} problems in {t_sample:.1f}s, "
                    f"extrapolated to m={w.m}"),
+        "host": host_info(),
     }
+    # context: the paper's own algorithm (Alg. 5) on the same cores, one
+    # block of SNPs timed after the factorization and the fixed part
+    t0 = time.time()
+    L = orc.cholesky_lower(M)
+    orc.fixed_blocks(L, XL, Y)
+    t_pre = time.time() - t0
+    nb = min(w.block, 2048)
+    XR = dg.make_XR(w, 0, nb)
+    t0 = time.time()
+    orc.hp_gwas_host(M, XL, XR, Y, w.p_R, block=nb, L=L)
+    t_blk = time.time() - t0
+    out["context_alg5"] = {
+        "value": w.m / (t_pre + t_blk / nb * w.m), "unit": "b_i/s", "kind": "context",
+        "sample": (f"paper's Alg. 5 (hp-gwas) with numpy/scipy BLAS on the host: Cholesky + fixed "
+                   f"part {t_pre:.1f}s, one block of {nb} problems {t_blk:.1f}s, extrapolated to m={w.m}"),
+    }
+    return out
+
+
+def host_info():
+    """The machine's host CPU: model name and logical cores."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"cpu": model, "nproc": os.cpu_count()}
 
 
 def stream_bench(args):
@@ -455,7 +506,8 @@ def main():
     if args.cpu_seconds > 0:
         log("cpu baseline (oracle) ...")
         cpu = cpu_baseline(w, M, XL, Y, args.cpu_seconds, lu=lu, t_factor=t_factor)
-        log(f"cpu: {cpu['value']:.1f} b_i/s ({cpu['sample']})")
+        log(f"cpu: {cpu['value']:.1f} b_i/s ({cpu['sample']}); context Alg. 5: "
+            f"{cpu['context_alg5']['value']:.1f} b_i/s ({cpu['context_alg5']['sample']})")
 
     head = results[forms[0]]
     roofline = {
@@ -469,6 +521,18 @@ def main():
         "step_tflops": round(head["step_tflops"], 3),
         "step_frac": round(head["step_tflops"] / head["peak"], 4),
         "assemble_avg_launch_ms": round(head["assemble_avg_ms"], 4),
+        # the diagonal steps W_k = inv(L_kk) R_k: about NB / n of the MFMA work
+        "diag_flop_share": round(128.0 / w.n, 4),
+        # the assembly's stream of whitened genotypes: 8 n_pad bytes per column
+        "assemble_gbps": round(8.0 * (-(-w.n // 128) * 128) * m * w.p_R / head["trsm_launches"]
+                               * args.steps / (head["assemble_avg_ms"] * 1e-3) / 1e9, 1),
+    }
+    phases = {
+        "factor_ms": round(head["factor_ms"], 2), "fixed_ms": round(head["fixed_ms"], 2),
+        "solve_ms": round(head["solve_ms"], 2),
+        "solve_only_value": round(m / (head["solve_ms"] * 1e-3), 1),
+        # int8 genotypes consumed per second of the step (tiny: the path is MFMA-bound)
+        "genotype_gbps": round(float(w.n) * m * w.p_R / (head["ms_per_step"] * 1e-3) / 1e9, 2),
     }
     form_out = {}
     for prec in forms[1:]:
@@ -491,7 +555,7 @@ def main():
                    "m": m, "block": block, "blocks_per_launch": batch, "streams": args.streams,
                    "slab_cols": args.slab_cols,
                    "M": f"h*ZZ^T/q+(1-h)I+1e-3I, q={w.q}, h={w.h}", "parallelism": "1 GPU"},
-        "roofline": roofline, "cpu_baseline": cpu,
+        "roofline": roofline, "cpu_baseline": cpu, "phases": phases,
         "parity": parity.get(forms[0]), "forms": form_out,
         "baseline_note": "vs_baseline divides by the paper's 12-core CPU rate for the same "
                          "workload (816 s for m=10^6, Table 3): context, other hardware",

@@ -177,6 +177,18 @@ def test_cross_routes_agree():
     assert maxrel(_alg_hp_gwas(M, XL, XR, y, 1), b0) < 1e-11
 
 
+@pytest.mark.parametrize("p_R,t,block", [(1, 1, 4), (2, 3, 5), (3, 2, 100)])
+def test_host_hp_gwas_matches_definition(p_R, t, block):
+    """The oracle's host version of Alg. 5 (timed as context by the
+    benchmark) reaches the definition's b_i, across block boundaries."""
+    rng = np.random.default_rng(11 + p_R)
+    M, XL, XR, Y = rand_problem(rng, n=60, p_L=3, p_R=p_R, m=11, t=t)
+    ref = orc.gls_sequence(M, XL, XR, Y, p_R)
+    got = orc.hp_gwas_host(M, XL, XR, Y, p_R, block=block)
+    assert got.shape == ref.shape
+    assert maxrel(got, ref) < 1e-11
+
+
 # --- intermediate quantities ----------------------------------------------------
 def test_cholesky_pins():
     rng = np.random.default_rng(8)
