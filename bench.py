@@ -68,6 +68,13 @@ def parse():
                     help="offered load of the Poisson arrivals, relative to 50 TFLOP/s")
     ap.add_argument("--serve-m-max", type=float, default=2e6,
                     help="upper end of the log-uniform m range (the full mix uses 1e7)")
+    ap.add_argument("--stream-source", choices=("generator", "file"), default="generator",
+                    help="stream workload: genotypes from the host generator or from a file "
+                         "read by the library's reader (written first, removed after)")
+    ap.add_argument("--stream-file", default=None,
+                    help="genotype file for --stream-source file (default: under $TMPDIR)")
+    ap.add_argument("--stream-direct", type=int, default=1,
+                    help="read the genotype file with O_DIRECT (page cache bypassed) when possible")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (for scaling HBM counters)")
     return ap.parse_args()
@@ -327,7 +334,18 @@ def stream_bench(args):
     dM = torch.from_numpy(M).cuda()
     dXL = torch.from_numpy(np.asfortranarray(XL)).cuda()
     dY = torch.from_numpy(np.asfortranarray(Y)).cuda()
-    fill, ctx = stream.workload_fill(w)
+    src = None
+    if args.stream_source == "file":
+        import tempfile
+        path = args.stream_file or os.path.join(tempfile.gettempdir(),
+                                                f"gls_genotypes_n{w.n}_m{m}.bin")
+        t0 = time.time()
+        nbytes = stream.write_genotype_file(path, w, m)
+        log(f"genotype file {path}: {nbytes / 1e9:.2f} GB written in {time.time() - t0:.1f}s")
+        src = stream.FileSource(path, w.n, w.p_R, direct=bool(args.stream_direct), threads=8)
+        fill, ctx = src.fill, src.ctx
+    else:
+        fill, ctx = stream.workload_fill(w)
     res, outs = {}, {}
     for prec in forms:
         t0 = time.perf_counter()
@@ -338,7 +356,9 @@ def stream_bench(args):
         setup_ms = (time.perf_counter() - t0) * 1e3
         stream.solve_stream(c, 0, min(m, 2 * block), block, w.p_R, fill, ctx)  # warm-up
         c.set_kernel_timing(True)
+        read0 = src.stats() if src else (0, 0.0)
         B, info, st = stream.solve_stream(c, 0, m, block, w.p_R, fill, ctx)
+        read1 = src.stats() if src else (0, 0.0)
         dev_ms = c.kernel_time(0)[0] + c.kernel_time(1)[0]
         c.set_kernel_timing(False)
         # in-core: the same problems with the genotypes resident, 4 blocks per launch
@@ -381,9 +401,15 @@ def stream_bench(args):
             "per_block_fill_ms": round(st["fill_ms"] / st["blocks"], 2),
             "factor_and_whiten_ms": round(setup_ms, 1),
         }
+        if src:
+            rb, rms = read1[0] - read0[0], read1[1] - read0[1]
+            res[prec]["file_read_gbps"] = round(rb / max(rms, 1e-9) / 1e6, 2)
         outs[prec] = B
         log(f"[{prec}] streamed {m / wall_s:.0f} b_i/s (device {dev_ms:.0f} of {st['wall_ms']:.0f} ms, "
             f"fill {st['fill_ms']:.0f} ms), in-core {m / in_core_s:.0f} b_i/s, bitwise equal {same}")
+    if src:
+        src.close()
+        os.remove(path)
     parity = {}
     if args.parity_sample > 0:
         lu = sla.lu_factor(M)
@@ -396,7 +422,10 @@ def stream_bench(args):
         "vs_baseline": None, "dtype": "f64" if forms[0] == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "p": w.p, "p_L": w.p_L, "p_R": w.p_R, "t": w.t,
-                   "m": m, "block": block, "source": "host C generator into pinned double buffers",
+                   "m": m, "block": block,
+                   "source": ("file read by gls_file_fill (written before the run, "
+                              + ("O_DIRECT" if args.stream_direct else "buffered") + ")")
+                   if src else "host C generator into pinned double buffers",
                    "parallelism": "1 GPU"},
         "forms": {k: {**v, **parity.get(k, {})} for k, v in res.items()},
     }

@@ -60,7 +60,9 @@ enum {
   GLS_E_STATE = 2,       /* call out of order (e.g. solve before whiten)  */
   GLS_E_OOM = 3,         /* device allocation failed                      */
   GLS_E_HIP = 4,         /* a HIP runtime call failed                     */
-  GLS_E_UNSUPPORTED = 5  /* valid but unsupported request                 */
+  GLS_E_UNSUPPORTED = 5, /* valid but unsupported request                 */
+  GLS_E_IO = 6,          /* a file could not be opened or read            */
+  GLS_E_ABORTED = 7      /* a stream callback returned nonzero            */
 };
 
 /* Factor M = L L^T (Cholesky; the potrf of Alg. 3-5, done once per
@@ -186,6 +188,8 @@ int gls_kernel_time(gls_handle h, int kind, double* ms, int64_t* launches);
  * sink(sink_ctx, snp0, nsnp, b, info) receives host pointers to the
  *   (nsnp, t, p) results and nsnp info codes of those problems, valid during
  *   the call; sinks are called in block order; nonzero aborts.
+ * A callback's abort makes the call return GLS_E_ABORTED once the device
+ *   work in flight has drained.
  * fill and sink work per block; the device solves superblocks of several
  * consecutive blocks (at least one slab of columns per compute unit per
  * launch), which changes no result bit.
@@ -210,6 +214,35 @@ typedef struct {
 int gls_solve_stream(gls_handle h, int64_t snp_begin, int64_t snp_end, int64_t block,
                      int64_t p_R, gls_fill_fn fill, void* fill_ctx, gls_sink_fn sink,
                      void* sink_ctx, gls_stream_stats* stats);
+
+/* ---- genotypes from a file (disk-backed out-of-core, Sec. 4, Alg. 8) ----
+ * A ready-made fill callback for gls_solve_stream that reads the genotypes
+ * from a file, as the paper's out-of-core algorithm reads the next block
+ * from disk while the current one is solved.  The file holds X_R
+ * column-major as int8 with leading dimension n: problem s, genotype column
+ * q at byte  offset + (s*p_R + q)*n; a block of problems is one contiguous
+ * range.  HOST code only (no device work, no HIP call).
+ * gls_file_open(out, path, n, p_R, offset, direct, threads) opens path for
+ *   reading; with direct != 0 it also opens it with O_DIRECT (page cache
+ *   bypassed; pieces whose file offset or length are not multiples of 4096
+ *   bytes, and files that refuse direct reads, go through the buffered
+ *   descriptor; destinations that refuse direct transfers, such as the
+ *   runtime's pinned buffers on some systems, are served through an aligned
+ *   bounce buffer per reader).  Each fill splits its range over `threads`
+ *   (1..64) reader threads.  Returns 0, a negative argument index, GLS_E_OOM
+ *   or GLS_E_IO (cannot open).
+ * gls_file_fill has the gls_fill_fn signature (pass the source as fill_ctx);
+ *   it requires ld == n and returns nonzero on an I/O error or a read past
+ *   the end of the file, which aborts the stream.
+ * gls_file_stats reports the bytes read and the wall time spent in fills.
+ * gls_file_close closes the file and releases the source (NULL is a no-op).
+ * A source may serve one stream at a time. */
+typedef struct gls_file_source_s* gls_file_source;
+int gls_file_open(gls_file_source* out, const char* path, int64_t n, int64_t p_R, int64_t offset,
+                  int direct, int threads);
+int gls_file_fill(void* source, int64_t snp0, int64_t nsnp, int8_t* buf, int64_t ld);
+int gls_file_stats(gls_file_source src, int64_t* bytes, double* ms);
+void gls_file_close(gls_file_source src);
 
 /* ---- several cohorts in one launch (serving) ----------------------------
  * One work item per block of problems of one handle.  All items are

@@ -274,6 +274,8 @@ const char* gls_strerror(int code) {
     case GLS_E_OOM: return "device memory allocation failed";
     case GLS_E_HIP: return "HIP runtime error";
     case GLS_E_UNSUPPORTED: return "unsupported request";
+    case GLS_E_IO: return "file could not be opened or read";
+    case GLS_E_ABORTED: return "a stream callback asked to stop";
     default: return code < 0 ? "invalid argument" : "unknown error";
   }
 }
@@ -659,7 +661,7 @@ int gls_solve_stream(gls_handle h, int64_t snp_begin, int64_t snp_end, int64_t b
       const auto ts = clk::now();
       const int r = sink(sink_ctx, sb_snp0(j) + o, nb, hB[sj] + (size_t)o * t * p, hinfo[sj] + o);
       st.sink_ms += ms_since(ts);
-      if (r) return GLS_E_STATE;
+      if (r) return GLS_E_ABORTED;
       st.blocks++;
     }
     st.bytes_d2h += (int64_t)(len * (t * p * sizeof(double) + sizeof(int32_t)));
@@ -681,7 +683,7 @@ int gls_solve_stream(gls_handle h, int64_t snp_begin, int64_t snp_end, int64_t b
       st.fill_ms += ms_since(tf);
       if (fr) {
         cleanup();
-        return GLS_E_STATE;
+        return GLS_E_ABORTED;
       }
     }
     // device input sj is free once the solve of superblock j-2 has finished

@@ -28,12 +28,14 @@ GLS_FP32_REFINE = 1
 PRECISIONS = {"fp64": GLS_FP64, "fp32_refine": GLS_FP32_REFINE}
 
 GLS_OK, GLS_E_NOT_SPD, GLS_E_STATE, GLS_E_OOM, GLS_E_HIP, GLS_E_UNSUPPORTED = 0, 1, 2, 3, 4, 5
+GLS_E_IO, GLS_E_ABORTED = 6, 7
 
 EXPORTS = ("gls_factor", "gls_whiten_fixed", "gls_solve_block", "gls_reserve", "gls_free",
            "gls_fork", "gls_set_stream", "gls_footprint_bytes", "gls_last_info",
            "gls_strerror", "gls_copy_factor", "gls_copy_fixed", "gls_whiten_block",
            "gls_solve_multi", "gls_set_slab_cols", "gls_set_kernel_timing", "gls_kernel_time",
-           "gls_solve_stream")
+           "gls_solve_stream", "gls_file_open", "gls_file_fill", "gls_file_stats",
+           "gls_file_close")
 
 _i64, _p, _int = ctypes.c_int64, ctypes.c_void_p, ctypes.c_int
 
@@ -90,6 +92,11 @@ def lib() -> ctypes.CDLL:
                                        ctypes.POINTER(_i64)]),
             "gls_solve_stream": (_int, [_p, _i64, _i64, _i64, _i64, _p, _p, _p, _p,
                                         ctypes.POINTER(gls_stream_stats)]),
+            "gls_file_open": (_int, [ctypes.POINTER(_p), ctypes.c_char_p, _i64, _i64, _i64, _int,
+                                     _int]),
+            "gls_file_fill": (_int, [_p, _i64, _i64, _p, _i64]),
+            "gls_file_stats": (_int, [_p, ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double)]),
+            "gls_file_close": (None, [_p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -201,6 +208,27 @@ def gls_solve_stream(h, snp_begin, snp_end, block, p_R, fill, fill_ctx, sink, si
 
 
 # ---- torch convenience ---------------------------------------------------------
+def gls_file_open(path: str, n: int, p_R: int, offset: int = 0, direct: bool = False,
+                  threads: int = 8) -> Tuple[int, int]:
+    h = _p()
+    rc = lib().gls_file_open(ctypes.byref(h), os.fsencode(path), n, p_R, offset, int(direct), threads)
+    return rc, h.value
+
+
+def gls_file_fill(src, snp0, nsnp, buf, ld) -> int:
+    return lib().gls_file_fill(src, snp0, nsnp, buf, ld)
+
+
+def gls_file_stats(src) -> Tuple[int, int, float]:
+    b, ms = _i64(), ctypes.c_double()
+    rc = lib().gls_file_stats(src, ctypes.byref(b), ctypes.byref(ms))
+    return rc, b.value, ms.value
+
+
+def gls_file_close(src) -> None:
+    lib().gls_file_close(src)
+
+
 def _torch():
     import torch
     return torch

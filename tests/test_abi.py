@@ -62,8 +62,9 @@ def test_argument_validation_without_device():
 
 
 def test_strerror_codes():
-    for code in range(0, 6):
-        assert gls.strerror(code)
+    for code in range(0, 8):
+        assert gls.strerror(code) != "unknown error"
+    assert gls.strerror(8) == "unknown error"
     assert gls.strerror(-3) == "invalid argument"
     assert "positive definite" in gls.strerror(gls.GLS_E_NOT_SPD)
 

@@ -68,8 +68,9 @@ def test_stream_abort_and_resume(mods):
         done.append(snp0 + nsnp)
         return len(done) < 3
 
-    with pytest.raises(gls.GLSError):
+    with pytest.raises(gls.GLSError) as e:
         stream.solve_stream(c, 0, W.m, W.block, W.p_R, fill, ctx, out=out, on_block=stop_after_three)
+    assert e.value.code == 7                           # GLS_E_ABORTED
     resume = done[-1]
     assert resume == 3 * W.block
     stream.solve_stream(c, resume, W.m, W.block, W.p_R, fill, ctx, out=out)
@@ -99,3 +100,29 @@ def test_stream_python_fill(mods):
 def ctypes_cast(addr):
     import ctypes
     return ctypes.cast(addr, ctypes.POINTER(ctypes.c_int8))
+
+
+@pytest.mark.parametrize("direct", [False, True])
+def test_stream_from_file_equals_generator(mods, tmp_path, direct):
+    """Disk-backed form: the genotypes written to a file and read back by the
+    library's reader (gls_file_fill) give the same bits as the in-memory
+    generator; a file shorter than the run aborts the stream cleanly."""
+    gls, stream = mods
+    say("stream from file, direct", direct)
+    c, *_ = cohort(gls, W)
+    fill, ctx = stream.workload_fill(W)
+    ref, _, _ = stream.solve_stream(c, 0, W.m, W.block, W.p_R, fill, ctx)
+    path = str(tmp_path / "genotypes.bin")
+    stream.write_genotype_file(path, W, W.m)
+    with stream.FileSource(path, W.n, W.p_R, direct=direct, threads=4) as src:
+        B, info, st = stream.solve_stream(c, 0, W.m, W.block, W.p_R, src.fill, src.ctx)
+        nbytes, _ = src.stats()
+    assert np.array_equal(B, ref) and np.all(info == 0)
+    assert nbytes == W.n * W.p_R * W.m
+    short = str(tmp_path / "short.bin")
+    stream.write_genotype_file(short, W, W.m - 3 * W.block)
+    with stream.FileSource(short, W.n, W.p_R) as src:
+        with pytest.raises(gls.GLSError) as e:
+            stream.solve_stream(c, 0, W.m, W.block, W.p_R, src.fill, src.ctx)
+        assert e.value.code == 7                       # GLS_E_ABORTED: the fill failed
+    c.free()
