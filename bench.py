@@ -38,7 +38,8 @@ PEAK_HBM_GBS = 8000.0
 # the paper's in-core/out-of-core time for n=10^4, p=4, m=10^6 on 12 Xeon
 # cores (Table 3): 816 s, i.e. 1,225 solves/s
 PAPER_BI_PER_S = 1_000_000 / 816.0
-WORKLOADS = {"scale": dg.SCALE, "mixed": dg.MIXED, "stream": dg.STREAM, "serve": dg.SERVE_BASE}
+WORKLOADS = {"scale": dg.SCALE, "mixed": dg.MIXED, "stream": dg.STREAM, "serve": dg.SERVE_BASE,
+             "ablation": dg.SCALE}
 
 
 def log(*a):
@@ -432,6 +433,74 @@ def stream_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def ablation_bench(args):
+    """The grouping ablation of the paper's Fig. 2 on the GPU (n = 10^4, p = 4):
+    the same whitening and per-problem solves with the genotype columns
+    grouped into launches of 64 .. 16,384 right-hand sides (1 .. 256 slabs of
+    64 columns for 256 compute units).  The paper groups many trsv into one
+    trsm for BLAS-3 efficiency on a CPU; on the GPU the grouping is what
+    fills the chip, and a launch of one slab leaves 255 compute units idle.
+    Each setting runs about a second of launches; the rate is problems per
+    second of wall time (factorization and fixed part excluded)."""
+    import torch
+    from paper_1210_7325_amd import gls
+    w = dg.SCALE
+    torch.cuda.set_device(0)
+    M = dg.make_M(w)
+    dM = torch.from_numpy(M).cuda()
+    dXL = torch.from_numpy(np.asfortranarray(dg.make_XL(w))).cuda()
+    dY = torch.from_numpy(np.asfortranarray(dg.make_Y(w))).cuda()
+    c = gls.Cohort(dM).whiten_fixed(dXL, dY, intercept_col=0)
+    rows = []
+    mmax = 4 * 16384
+    dXR = upload_genotypes(torch, w, mmax)
+    B = torch.empty((mmax, w.t, w.p), dtype=torch.float64, device="cuda")
+    info = torch.empty((mmax,), dtype=torch.int32, device="cuda")
+    for cols in (64, 256, 1024, 4096, 16384):
+        batch = max(1, cols // 4096)
+        block = cols // batch
+        hs = [c] + [c.fork(torch.cuda.current_stream()) for _ in range(batch - 1)]
+        for h in hs:
+            h.reserve(block)
+        launches = max(2, min(mmax // cols, 4))
+
+        def run():
+            for L in range(launches):
+                items = []
+                for j in range(batch):
+                    a = (L * batch + j) * block
+                    items.append((hs[j], dXR[:, a:a + block], 1, B[a:a + block], info[a:a + block]))
+                gls.solve_multi(items)
+            torch.cuda.synchronize()
+        run()
+        t0 = time.perf_counter()
+        run()
+        dt = time.perf_counter() - t0
+        rate = launches * cols / dt
+        rows.append({"rhs_per_launch": cols, "slabs_per_launch": cols // 64,
+                     "ms_per_launch": round(dt / launches * 1e3, 3), "value": round(rate, 1),
+                     "tflops": round(float(w.n) ** 2 * rate / 1e12, 2)})
+        log(f"[ablation] {cols:6d} RHS per launch: {rate:10.0f} b_i/s, {dt / launches * 1e3:.2f} ms/launch")
+        for h in hs[1:]:
+            h.free()
+    c.free()
+    head = rows[-1]
+    out = {
+        "metric": "GLS solves/sec vs right-hand sides grouped per launch (n=1e4, p=4)",
+        "value": head["value"], "unit": "b_i/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": head["ms_per_launch"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "ablation_grouping_n10000_p4", "n": w.n, "p": w.p,
+                   "parallelism": "1 GPU"},
+        "grouping": rows,
+        "grouping_gain": round(rows[-1]["value"] / rows[0]["value"], 1),
+        "note": ("per-problem whitening of the whole X_i (the paper's seq-gls structure) would add "
+                 f"a factor p = {w.p} of trsm work; a per-problem trsv reads L (n^2/2 doubles) "
+                 "once per problem, at most 8 TB/s / 400 MB = 2e4 problems/s at n = 1e4"),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def serve_bench(args):
     """The serving mix: Poisson arrivals of GWAS jobs (n in {1500, 4000,
     10000, 20000}, p uniform in 4..20, m log-uniform in [1e5, m_max], each
@@ -487,6 +556,9 @@ def main():
         return
     if args.workload == "serve" and args.gpus == 1:
         serve_bench(args)
+        return
+    if args.workload == "ablation" and args.gpus == 1:
+        ablation_bench(args)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
