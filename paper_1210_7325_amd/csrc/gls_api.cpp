@@ -75,7 +75,11 @@ template <typename T>
 int dalloc(T** p, size_t count) {
   *p = nullptr;
   if (count == 0) count = 1;
-  return hip_code(hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T)));
+  const hipError_t e = hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
+  // a failed allocation also sets the runtime's last error; clear it so the
+  // launch checks of later calls do not report it again
+  if (e != hipSuccess) (void)hipGetLastError();
+  return hip_code(e);
 }
 
 template <typename T>
