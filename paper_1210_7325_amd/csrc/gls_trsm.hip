@@ -14,6 +14,13 @@ namespace gls {
 //   W_k = inv(L_kk) R_k                FP64 MFMA, R_k staged in LDS
 // The waves split the NB rows of a block (WR ways) and the C columns (WC
 // ways).  X is int8 genotypes (exact in FP64) or FP64 (fixed part).
+// True when the last row block's real rows (n - (K-1) NB of them) all lie in
+// the first of the WR wave rows' tiles (RW rows): the rest of that block is
+// padding, whose R and W are zero, and k_trsm_last solves it.
+__host__ __device__ inline bool last_block_split(int64_t n, int K, int RW) {
+  return K > 1 && n - (int64_t)(K - 1) * NB <= RW;
+}
+
 template <int C, int WR, int WC, int D, typename TIn>
 __global__ __launch_bounds__(64 * WR * WC) void k_trsm(const JobTable tab) {
   constexpr int RW = NB / WR, RT = RW / 16;
@@ -37,11 +44,15 @@ __global__ __launch_bounds__(64 * WR * WC) void k_trsm(const JobTable tab) {
   const double* __restrict__ LinvP = J.LinvP;
   double* __restrict__ Wslab = J.W + slab * (int64_t)K * NB * C;
 
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  // the wave index is wave-uniform (kept in scalar registers)
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x % 64;
   const int wr = wave / WC, wc = wave % WC;
   const int64_t col_base = slab * C + wc * CW;
 
-  for (int k = 0; k < K; k++) {
+  // the last row block is left to k_trsm_last when all of its real rows
+  // lie in the first wave row's tile
+  const int Kmain = last_block_split(n, K, RW) ? K - 1 : K;
+  for (int k = 0; k < Kmain; k++) {
     // this block's right-hand side, loaded early (consumed after the GEMM)
     double xv[RT][CT][4];
 #pragma unroll
@@ -157,6 +168,149 @@ __global__ __launch_bounds__(64 * WR * WC) void k_trsm(const JobTable tab) {
   }
 }
 
+// The last row block of every slab when last_block_split holds, after
+// k_trsm has solved the others (same grid, one work-group per slab).  Its
+// GEMM covers only the first RW rows (the only real ones), and the WR wave
+// rows share it: wave row w sums its quarter of the k NB/8 pairs for that
+// tile; the partial sums meet in LDS in a fixed order, then the diagonal
+// step W = inv(L_kk) R and the store run as in k_trsm (rows beyond the first
+// tile give W = 0, as padding must).  Without this, one wave row would do
+// the whole GEMM while the others multiply padding.
+template <int C, int WR, int WC, int D>
+__global__ __launch_bounds__(64 * WR * WC) void k_trsm_last(const JobTable tab) {
+  constexpr int RW = NB / WR, RT = RW / 16;
+  constexpr int CW = C / WC, CT = CW / 16;
+  constexpr int CTS = C / 16;
+  constexpr int NPB = NB / 8;
+  __shared__ __attribute__((aligned(16))) double Rl[NB * C];
+
+  int jb = 0;
+  while (jb + 1 < tab.njobs && (int64_t)blockIdx.x >= tab.j[jb + 1].slab0) jb++;
+  const JobDesc& J = tab.j[jb];
+  const int K = J.K;
+  if (!last_block_split(J.n, K, RW)) return;
+  const int k = K - 1;
+  const int64_t slab = (int64_t)blockIdx.x - J.slab0;
+  const int8_t* __restrict__ X = reinterpret_cast<const int8_t*>(J.X);
+  double* __restrict__ Wslab = J.W + slab * (int64_t)K * NB * C;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x % 64;
+  const int wr = wave / WC, wc = wave % WC;
+  const int64_t col_base = slab * C + wc * CW;
+
+  // the first tile's right-hand side, added by the first wave row only
+  const double xs = wr == 0 ? 1.0 : 0.0;
+  double xv[RT][CT][4];
+#pragma unroll
+  for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+    for (int ct = 0; ct < CT; ct++)
+#pragma unroll
+      for (int i = 0; i < 4; i++)
+        xv[rt][ct][i] = load_x<int8_t>(X, J.ldx, (int64_t)k * NB + rt * 16 + lane / 16 + 4 * i,
+                                       col_base + ct * 16 + lane % 16, J.n, J.ncols);
+  d4 acc[RT][CT];
+#pragma unroll
+  for (int a = 0; a < RT; a++)
+#pragma unroll
+    for (int b = 0; b < CT; b++) acc[a][b] = (d4){0, 0, 0, 0};
+  const double* __restrict__ Ls = J.Lstrips + strip_offset(k) + lane * 2;  // row tile 0
+  const double* __restrict__ Wb = Wslab + (size_t)(wc * CT) * 128 + lane * 2;
+  const int nq = k * NPB / D;
+  const int p0 = nq * wr / WR * D, p1 = nq * (wr + 1) / WR * D;
+  if (p1 > p0) {
+    d2 a[D][RT], b[D][CT];
+#pragma unroll
+    for (int s = 0; s < D; s++) {
+#pragma unroll
+      for (int rt = 0; rt < RT; rt++)
+        a[s][rt] = *reinterpret_cast<const d2*>(Ls + ((size_t)(p0 + s) * (NB / 16) + rt) * 128);
+#pragma unroll
+      for (int ct = 0; ct < CT; ct++)
+        b[s][ct] = *reinterpret_cast<const d2*>(Wb + ((size_t)(p0 + s) * CTS + ct) * 128);
+      asm volatile("" ::: "memory");
+    }
+    for (int kp0 = p0; kp0 < p1; kp0 += D) {
+#pragma unroll
+      for (int s = 0; s < D; s++) {
+#pragma unroll
+        for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+          for (int ct = 0; ct < CT; ct++) {
+            acc[rt][ct] = MFMA64(a[s][rt].x, b[s][ct].x, acc[rt][ct]);
+            acc[rt][ct] = MFMA64(a[s][rt].y, b[s][ct].y, acc[rt][ct]);
+          }
+        int nx = kp0 + s + D;
+        nx = nx < p1 ? nx : p1 - 1;
+#pragma unroll
+        for (int rt = 0; rt < RT; rt++)
+          a[s][rt] = *reinterpret_cast<const d2*>(Ls + ((size_t)nx * (NB / 16) + rt) * 128);
+#pragma unroll
+        for (int ct = 0; ct < CT; ct++)
+          b[s][ct] = *reinterpret_cast<const d2*>(Wb + ((size_t)nx * CTS + ct) * 128);
+        asm volatile("" ::: "memory");
+      }
+    }
+  }
+  // partial sums into this wave row's own rows of Rl; the first wave row's
+  // rows (one contiguous run of RW C doubles) then gather them
+#pragma unroll
+  for (int rt = 0; rt < RT; rt++) {
+    const int rowl = wr * RW + rt * 16;
+#pragma unroll
+    for (int ct = 0; ct < CT; ct++)
+#pragma unroll
+      for (int i = 0; i < 4; i += 2) {
+        const int kp = (rowl / 4 + i) / 2;
+        *reinterpret_cast<d2*>(&Rl[((size_t)kp * CTS + wc * CT + ct) * 128 + lane * 2]) =
+            (d2){xs * xv[rt][ct][i] - acc[rt][ct][i], xs * xv[rt][ct][i + 1] - acc[rt][ct][i + 1]};
+      }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < RW * C; i += 64 * WR * WC) {
+    double v = Rl[i];
+#pragma unroll
+    for (int w = 1; w < WR; w++) {
+      v += Rl[(size_t)w * RW * C + i];
+      Rl[(size_t)w * RW * C + i] = 0.0;
+    }
+    Rl[i] = v;
+  }
+  __syncthreads();
+  // W_k = inv(L_kk) R_k and the store, as in k_trsm
+#pragma unroll
+  for (int a = 0; a < RT; a++)
+#pragma unroll
+    for (int b = 0; b < CT; b++) acc[a][b] = (d4){0, 0, 0, 0};
+  const double* __restrict__ Li = J.LinvP + (size_t)k * NB * NB + (size_t)(wr * RT) * 128 + lane * 2;
+  const int kp_end = (wr * RW + RW) / 8;
+  for (int kp = 0; kp < kp_end; kp++) {
+    d2 a[RT], b[CT];
+#pragma unroll
+    for (int rt = 0; rt < RT; rt++)
+      a[rt] = *reinterpret_cast<const d2*>(Li + ((size_t)kp * (NB / 16) + rt) * 128);
+#pragma unroll
+    for (int ct = 0; ct < CT; ct++)
+      b[ct] = *reinterpret_cast<const d2*>(&Rl[((size_t)kp * CTS + wc * CT + ct) * 128 + lane * 2]);
+#pragma unroll
+    for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+      for (int ct = 0; ct < CT; ct++) {
+        acc[rt][ct] = MFMA64(a[rt].x, b[ct].x, acc[rt][ct]);
+        acc[rt][ct] = MFMA64(a[rt].y, b[ct].y, acc[rt][ct]);
+      }
+  }
+#pragma unroll
+  for (int rt = 0; rt < RT; rt++) {
+    const int64_t ks0 = (int64_t)k * (NB / 4) + (wr * RW + rt * 16) / 4;
+#pragma unroll
+    for (int ct = 0; ct < CT; ct++)
+#pragma unroll
+      for (int i = 0; i < 4; i += 2)
+        *reinterpret_cast<d2*>(Wslab + ((size_t)((ks0 + i) / 2) * CTS + wc * CT + ct) * 128 + lane * 2) =
+            (d2){acc[rt][ct][i], acc[rt][ct][i + 1]};
+  }
+}
+
 // Slab layout -> caller's column-major array (inspection).
 __global__ void k_slab_to_colmajor(const double* __restrict__ W, int C, int64_t n_pad, int64_t n,
                                    int64_t col0, int64_t ncols, double* __restrict__ out, int64_t ldo) {
@@ -169,10 +323,23 @@ __global__ void k_slab_to_colmajor(const double* __restrict__ W, int C, int64_t 
 
 
 hipError_t launch_trsm_i8(const JobTable& tab, int64_t nslabs, int C, hipStream_t st) {
+  // the last row block goes to k_trsm_last when some job of the table wants
+  // it (WR = 4 wave rows of NB / 4 rows in every configuration)
+  bool last = false;
+  for (int i = 0; i < tab.njobs; i++) last = last || last_block_split(tab.j[i].n, tab.j[i].K, NB / 4);
   switch (C) {
-    case 16: k_trsm<16, 4, 1, TRSM_DEPTH, int8_t><<<(unsigned)nslabs, 256, 0, st>>>(tab); break;
-    case 32: k_trsm<32, 4, 2, TRSM_DEPTH, int8_t><<<(unsigned)nslabs, 512, 0, st>>>(tab); break;
-    case 64: k_trsm<64, 4, 2, TRSM_DEPTH, int8_t><<<(unsigned)nslabs, 512, 0, st>>>(tab); break;
+    case 16:
+      k_trsm<16, 4, 1, TRSM_DEPTH, int8_t><<<(unsigned)nslabs, 256, 0, st>>>(tab);
+      if (last) k_trsm_last<16, 4, 1, TRSM_DEPTH><<<(unsigned)nslabs, 256, 0, st>>>(tab);
+      break;
+    case 32:
+      k_trsm<32, 4, 2, TRSM_DEPTH, int8_t><<<(unsigned)nslabs, 512, 0, st>>>(tab);
+      if (last) k_trsm_last<32, 4, 2, TRSM_DEPTH><<<(unsigned)nslabs, 512, 0, st>>>(tab);
+      break;
+    case 64:
+      k_trsm<64, 4, 2, TRSM_DEPTH, int8_t><<<(unsigned)nslabs, 512, 0, st>>>(tab);
+      if (last) k_trsm_last<64, 4, 2, TRSM_DEPTH><<<(unsigned)nslabs, 512, 0, st>>>(tab);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
