@@ -57,7 +57,9 @@ def parse():
     ap.add_argument("--streams", type=int, default=1)
     ap.add_argument("--batch", type=int, default=None,
                     help="blocks whitened per launch (default: 4 / p_R)")
-    ap.add_argument("--slab-cols", type=int, default=64)
+    ap.add_argument("--slab-cols", type=int, default=0,
+                    help="columns per work-group of the solve: 16, 32, 64, or 0 to let the library "
+                         "choose per launch")
     ap.add_argument("--forms", default="fp64,fp32_refine",
                     help="precisions to time, the first is the headline")
     ap.add_argument("--parity-sample", type=int, default=1000,
@@ -93,7 +95,7 @@ def measured_traffic(batch, slab_cols, precision):
         kv = dict(l.split(": ", 1) for l in open(path).read().splitlines() if ": " in l)
         if kv.get("kernel_source_sha256") != trsm_source_digest() \
                 or int(kv["blocks_per_launch"]) != batch \
-                or slab_cols != 64:
+                or slab_cols not in (0, 64):
             return None
         return float(kv["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
@@ -436,12 +438,13 @@ def stream_bench(args):
 def ablation_bench(args):
     """The grouping ablation of the paper's Fig. 2 on the GPU (n = 10^4, p = 4):
     the same whitening and per-problem solves with the genotype columns
-    grouped into launches of 64 .. 16,384 right-hand sides (1 .. 256 slabs of
-    64 columns for 256 compute units).  The paper groups many trsv into one
+    grouped into launches of 64 .. 16,384 right-hand sides, with 64-column
+    slabs (1 .. 256 of them for 256 compute units) and with the library's
+    per-launch choice of slab width.  The paper groups many trsv into one
     trsm for BLAS-3 efficiency on a CPU; on the GPU the grouping is what
     fills the chip, and a launch of one slab leaves 255 compute units idle.
-    Each setting runs about a second of launches; the rate is problems per
-    second of wall time (factorization and fixed part excluded)."""
+    Each setting times four launches after a warm-up; the rate is problems
+    per second of wall time (factorization and fixed part excluded)."""
     import torch
     from paper_1210_7325_amd import gls
     w = dg.SCALE
@@ -456,7 +459,8 @@ def ablation_bench(args):
     dXR = upload_genotypes(torch, w, mmax)
     B = torch.empty((mmax, w.t, w.p), dtype=torch.float64, device="cuda")
     info = torch.empty((mmax,), dtype=torch.int32, device="cuda")
-    for cols in (64, 256, 1024, 4096, 16384):
+    for slab, cols in [(sc, cl) for sc in (64, 0) for cl in (64, 256, 1024, 4096, 16384)]:
+        c.set_slab_cols(slab)
         batch = max(1, cols // 4096)
         block = cols // batch
         hs = [c] + [c.fork(torch.cuda.current_stream()) for _ in range(batch - 1)]
@@ -477,14 +481,16 @@ def ablation_bench(args):
         run()
         dt = time.perf_counter() - t0
         rate = launches * cols / dt
-        rows.append({"rhs_per_launch": cols, "slabs_per_launch": cols // 64,
+        rows.append({"rhs_per_launch": cols, "slab_cols": slab or "auto",
                      "ms_per_launch": round(dt / launches * 1e3, 3), "value": round(rate, 1),
                      "tflops": round(float(w.n) ** 2 * rate / 1e12, 2)})
-        log(f"[ablation] {cols:6d} RHS per launch: {rate:10.0f} b_i/s, {dt / launches * 1e3:.2f} ms/launch")
+        log(f"[ablation] slabs {slab or 'auto'}: {cols:6d} RHS per launch: {rate:10.0f} b_i/s, "
+            f"{dt / launches * 1e3:.2f} ms/launch")
         for h in hs[1:]:
             h.free()
     c.free()
     head = rows[-1]
+    fixed = [r for r in rows if r["slab_cols"] == 64]
     out = {
         "metric": "GLS solves/sec vs right-hand sides grouped per launch (n=1e4, p=4)",
         "value": head["value"], "unit": "b_i/s", "n_gpus": 1, "steps": 1, "warmup": 1,
@@ -493,7 +499,8 @@ def ablation_bench(args):
         "config": {"workload": "ablation_grouping_n10000_p4", "n": w.n, "p": w.p,
                    "parallelism": "1 GPU"},
         "grouping": rows,
-        "grouping_gain": round(rows[-1]["value"] / rows[0]["value"], 1),
+        "grouping_gain_64_col_slabs": round(fixed[-1]["value"] / fixed[0]["value"], 1),
+        "grouping_gain_auto_slabs": round(rows[-1]["value"] / rows[len(fixed)]["value"], 1),
         "note": ("per-problem whitening of the whole X_i (the paper's seq-gls structure) would add "
                  f"a factor p = {w.p} of trsm work; a per-problem trsv reads L (n^2/2 doubles) "
                  "once per problem, at most 8 TB/s / 400 MB = 2e4 problems/s at n = 1e4"),
@@ -654,7 +661,7 @@ def main():
         "dtype": "f64" if forms[0] == "fp64" else "f32+f64", "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "p": w.p, "p_L": w.p_L, "p_R": w.p_R, "t": w.t,
                    "m": m, "block": block, "blocks_per_launch": batch, "streams": args.streams,
-                   "slab_cols": args.slab_cols,
+                   "slab_cols": args.slab_cols or "auto",
                    "M": f"h*ZZ^T/q+(1-h)I+1e-3I, q={w.q}, h={w.h}", "parallelism": "1 GPU"},
         "roofline": roofline, "cpu_baseline": cpu, "phases": phases,
         "parity": parity.get(forms[0]), "forms": form_out,

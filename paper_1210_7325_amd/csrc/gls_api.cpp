@@ -34,6 +34,7 @@ struct Cohort {
   double* STL = nullptr;       // pL x pL
   double* CT = nullptr;        // pL x t
   double* Z = nullptr;         // FP32_REFINE: row-major n_pad x (pL+t), M^{-1}[X_L | Y]
+  int cus = 256;               // compute units of the device the cohort lives on
 };
 
 }  // namespace
@@ -46,7 +47,7 @@ struct TimedLaunch {
 struct gls_handle_s {
   Cohort* c = nullptr;
   hipStream_t stream = nullptr;
-  int C = DEFAULT_C;           // columns per work-group of the triangular solve
+  int C = 0;                   // columns per work-group of the triangular solve; 0 = per launch
   double* W = nullptr;         // workspace: whitened genotype columns, slab layout
   int64_t Wcols = 0;           // capacity in columns (multiple of 64)
   float* W32 = nullptr;        // FP32_REFINE: FP32 copy of W (quad layout)
@@ -156,7 +157,7 @@ XzDesc make_xz(gls_handle h, int64_t grp0, int64_t ncols, const int8_t* X, int64
   return x;
 }
 
-AsmDesc make_asm(gls_handle h, int64_t grp0, int64_t nsnp, int64_t pR, double* B, int64_t ldb,
+AsmDesc make_asm(gls_handle h, int C, int64_t grp0, int64_t nsnp, int64_t pR, double* B, int64_t ldb,
                  int32_t* info) {
   AsmDesc a;
   a.grp0 = grp0;
@@ -170,7 +171,7 @@ AsmDesc make_asm(gls_handle h, int64_t grp0, int64_t nsnp, int64_t pR, double* B
   a.B = B;
   a.ldb = ldb;
   a.info = info;
-  a.C = h->C;
+  a.C = C;
   a.pL = (int)h->c->pL;
   a.pR = (int)pR;
   a.t = (int)h->c->t;
@@ -218,14 +219,38 @@ struct TimedScope {
   ~TimedScope() { end(); }
 };
 
+// Slab width of one launch.  A slab's walk down the row blocks takes about
+// the same time whatever else runs, so a launch of few columns is fastest
+// with the narrowest slabs that still give at most one work-group per
+// compute unit (measured at n = 10^4, FP64: 576 to 4,096 columns in 9.9 ms
+// with 16-column slabs against 22.9 ms with 64; 8,192 columns in 16.4 ms
+// with 32 against 23.3 ms), while launches that fill the chip are fastest
+// with 64.  The FP32_REFINE kernel has no 16-column form.  A width set on
+// the handle overrides the choice.
+int slab_cols_for(const gls_work* items, int64_t count) {
+  const gls_handle h = items[0].h;
+  if (h->C != 0) return h->C;
+  int64_t s16 = 0, s32 = 0;
+  for (int64_t i = 0; i < count; i++) {
+    const int64_t ncols = items[i].nsnp * items[i].p_R;
+    s16 += (ncols + 15) / 16;
+    s32 += (ncols + 31) / 32;
+  }
+  const int64_t cus = h->c->cus;
+  if (h->c->prec != GLS_FP32_REFINE && s16 <= cus) return 16;
+  if (s32 <= cus) return 32;
+  return 64;
+}
+
 // Launch the kernels of up to MAX_INLINE_JOBS checked work items (same slab
-// width and precision) on stream st; timing events go through handle th.
+// width setting and precision) on stream st; timing events go through
+// handle th.
 int launch_items(const gls_work* items, int64_t count, hipStream_t st, gls_handle th) {
   for (int64_t i = 0; i < count; i++) {
     int rc = ensure_workspace(items[i].h, items[i].nsnp * items[i].p_R);
     if (rc) return rc;
   }
-  const int C = items[0].h->C;
+  const int C = slab_cols_for(items, count);
   const bool refine = items[0].h->c->prec == GLS_FP32_REFINE;
   JobTable tab;
   AsmTable at;
@@ -242,7 +267,7 @@ int launch_items(const gls_work* items, int64_t count, hipStream_t st, gls_handl
     }
     tab.j[tab.njobs++] = make_job(w.h, slabs, ncols, w.X_R, w.ldxr);
     slabs += (ncols + C - 1) / C;
-    at.j[at.njobs++] = make_asm(w.h, groups, w.nsnp, w.p_R, w.B, w.ldb, w.info);
+    at.j[at.njobs++] = make_asm(w.h, C, groups, w.nsnp, w.p_R, w.B, w.ldb, w.info);
     const int64_t per_group = (AS_GROUP_COLS / 16) * (16 / w.p_R);  // problems per assembly work-group
     groups += (w.nsnp + per_group - 1) / per_group;
   }
@@ -316,6 +341,13 @@ int gls_factor(gls_handle* out, int64_t n, const double* M, int64_t ldm, int pre
   if (!c) return GLS_E_OOM;
   c->n = n;
   c->K = (int)((n + NB - 1) / NB);
+  {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+      c->cus = cus;
+    (void)hipGetLastError();
+  }
   c->n_pad = (int64_t)c->K * NB;
   c->prec = prec;
   gls_handle h = new (std::nothrow) gls_handle_s();
@@ -518,22 +550,24 @@ int gls_whiten_block(gls_handle h, int64_t ncols, const int8_t* X, int64_t ldx, 
   JobTable tab;
   tab.njobs = 1;
   tab.j[0] = make_job(h, 0, ncols, X, ldx);
+  const gls_work item{h, ncols, 1, X, ldx, nullptr, 0, nullptr};
+  const int C = slab_cols_for(&item, 1);
   TimedScope t0(h, 0);
   if (h->c->prec == GLS_FP32_REFINE) {
     // plain L^{-1} X: no centering shift
     HIPCHK(hipMemsetAsync(h->shift, 0, sizeof(double) * ncols, h->stream));
-    HIPCHK(launch_trsm_mixed(tab, (ncols + h->C - 1) / h->C, h->C, h->stream));
+    HIPCHK(launch_trsm_mixed(tab, (ncols + C - 1) / C, C, h->stream));
   } else {
-    HIPCHK(launch_trsm_i8(tab, (ncols + h->C - 1) / h->C, h->C, h->stream));
+    HIPCHK(launch_trsm_i8(tab, (ncols + C - 1) / C, C, h->stream));
   }
   t0.end();
-  HIPCHK(launch_slab_to_colmajor(h->W, h->C, h->c->n_pad, h->c->n, 0, ncols, W, ldw, h->stream));
+  HIPCHK(launch_slab_to_colmajor(h->W, C, h->c->n_pad, h->c->n, 0, ncols, W, ldw, h->stream));
   return GLS_OK;
 }
 
 int gls_set_slab_cols(gls_handle h, int cols) {
   if (!h) return -1;
-  if (cols != 16 && cols != 32 && cols != 64) return -2;
+  if (cols != 0 && cols != 16 && cols != 32 && cols != 64) return -2;
   if (h->c->prec == GLS_FP32_REFINE && cols == 16) return GLS_E_UNSUPPORTED;
   h->C = cols;
   return GLS_OK;
@@ -593,7 +627,7 @@ int gls_solve_stream(gls_handle h, int64_t snp_begin, int64_t snp_end, int64_t b
   // I/O happens per block of `block` problems; the device solves
   // superblocks of `group` consecutive blocks so that one launch has at
   // least one slab per CU (results do not depend on the grouping)
-  const int64_t target_cols = 256 * (int64_t)h->C;
+  const int64_t target_cols = h->c->cus * (int64_t)(h->C ? h->C : DEFAULT_C);
   const int64_t group = std::max<int64_t>(1, (target_cols + block * p_R - 1) / (block * p_R));
   const int64_t sbk = group * block;  // problems per superblock
   const int64_t cols = sbk * p_R;

@@ -167,6 +167,28 @@ def test_deterministic_and_block_independent(G):
     assert np.array_equal(B1, B3)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32_refine"])
+def test_slab_width_choice_is_bitwise_neutral(G, prec):
+    """Automatic per-launch slab width (the default) against every fixed
+    width: the same bits, for launches small enough to pick 16 or 32 and
+    large enough to pick 64 columns per work-group."""
+    say("slab widths", prec)
+    from paper_1210_7325_amd import gls
+    w, M, XL, Y, XR = small_problem(700, m=20000)
+    c = gls.Cohort(to_dev(M), precision=prec).whiten_fixed(to_dev(XL), to_dev(Y), intercept_col=0)
+    dXR = to_dev(XR)
+    widths = (32, 64) if prec == "fp32_refine" else (16, 32, 64)
+    for m in (100, 5000, 20000):
+        c.set_slab_cols(0)
+        ref, _ = c.solve_block(dXR[:, :m])
+        ref = ref.cpu().numpy()
+        for C in widths:
+            c.set_slab_cols(C)
+            B, _ = c.solve_block(dXR[:, :m])
+            assert np.array_equal(B.cpu().numpy(), ref), (m, C)
+    c.free()
+
+
 def test_multi_cohort_launch_equals_single(G):
     say("multi")
     from paper_1210_7325_amd import gls
