@@ -3,6 +3,13 @@
 
 namespace gls {
 
+// True when the last row block's real rows (n - (K-1) NB of them) all lie in
+// the first of the wave rows' tiles (RW rows); k_trsm_mixed_last then
+// solves that block.
+__host__ __device__ inline bool mixed_last_block_split(int64_t n, int K, int RW) {
+  return K > 1 && n - (int64_t)(K - 1) * NB <= RW;
+}
+
 // Mixed-precision blocked lower solve W = L^{-1}(X - 1 s^T): as k_trsm, but
 // each off-diagonal product L_kj W_j uses FP32-rounded operands on FP32 MFMA
 // (v_mfma_f32_16x16x4f32) with FP32 accumulation over one chunk of CHQ
@@ -38,7 +45,10 @@ __global__ __launch_bounds__(64 * WR * WC) void k_trsm_mixed(const JobTable tab)
   const int wr = wave / WC, wc = wave % WC;
   const int64_t col_base = slab * C + wc * CW;
 
-  for (int k = 0; k < K; k++) {
+  // the last row block is left to k_trsm_mixed_last when all of its real
+  // rows lie in the first wave row's tile
+  const int Kmain = mixed_last_block_split(n, K, RW) ? K - 1 : K;
+  for (int k = 0; k < Kmain; k++) {
     double xv[RT][CT][4];
 #pragma unroll
     for (int rt = 0; rt < RT; rt++)
@@ -184,10 +194,189 @@ __global__ __launch_bounds__(64 * WR * WC) void k_trsm_mixed(const JobTable tab)
 }
 
 
+// The last row block of every slab when mixed_last_block_split holds, after
+// k_trsm_mixed has solved the others (same grid): the wave rows share the
+// first tile's GEMM (FP32 chunks folded into FP64 per wave row, wave row w
+// over its quarter of the quads), the FP64 partial sums meet in LDS in a
+// fixed order, then the FP64 diagonal step and both stores run as in
+// k_trsm_mixed (rows beyond the first tile give W = 0, as padding must).
+template <int C, int WR, int WC, int D, int CHQ>
+__global__ __launch_bounds__(64 * WR * WC) void k_trsm_mixed_last(const JobTable tab) {
+  constexpr int RW = NB / WR, RT = RW / 16;
+  constexpr int CW = C / WC, CT = CW / 16;
+  constexpr int CTS = C / 16;
+  constexpr int NQB = NB / 16;
+  static_assert(CHQ == 1 || D % CHQ == 0, "chunks within one stage group");
+  __shared__ __attribute__((aligned(16))) double Rl[NB * C];
+
+  int jb = 0;
+  while (jb + 1 < tab.njobs && (int64_t)blockIdx.x >= tab.j[jb + 1].slab0) jb++;
+  const JobDesc& J = tab.j[jb];
+  const int K = J.K;
+  if (!mixed_last_block_split(J.n, K, RW)) return;
+  const int k = K - 1;
+  const int64_t slab = (int64_t)blockIdx.x - J.slab0;
+  const int8_t* __restrict__ X = reinterpret_cast<const int8_t*>(J.X);
+  const double* __restrict__ shift = J.shift;
+  double* __restrict__ Wslab = J.W + slab * (int64_t)K * NB * C;
+  float* __restrict__ W32slab = J.W32 + slab * (int64_t)K * NB * C;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x % 64;
+  const int wr = wave / WC, wc = wave % WC;
+  const int64_t col_base = slab * C + wc * CW;
+
+  // the first tile's centered right-hand side, added by the first wave row
+  const double xs = wr == 0 ? 1.0 : 0.0;
+  double xv[RT][CT][4];
+#pragma unroll
+  for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+    for (int ct = 0; ct < CT; ct++) {
+      const int64_t col = col_base + ct * 16 + lane % 16;
+#pragma unroll
+      for (int i = 0; i < 4; i++) {
+        const int64_t row = (int64_t)k * NB + rt * 16 + 4 * (lane / 16) + i;
+        xv[rt][ct][i] = (row < J.n && col < J.ncols) ? (double)X[col * J.ldx + row] - shift[col] : 0.0;
+      }
+    }
+  d4 acc[RT][CT];
+  f4 c32[RT][CT];
+#pragma unroll
+  for (int a = 0; a < RT; a++)
+#pragma unroll
+    for (int b = 0; b < CT; b++) {
+      acc[a][b] = (d4){0, 0, 0, 0};
+      c32[a][b] = (f4){0, 0, 0, 0};
+    }
+  const float* __restrict__ Ls = J.Lstrips32 + strip_offset(k) + lane * 4;  // row tile 0
+  const float* __restrict__ Wb = W32slab + (size_t)(wc * CT) * 256 + lane * 4;
+  const int ng = k * NQB / D;  // groups of D quads
+  const int q0b = ng * wr / WR * D, q1b = ng * (wr + 1) / WR * D;
+  if (q1b > q0b) {
+    f4 a[D][RT], b[D][CT];
+#pragma unroll
+    for (int s = 0; s < D; s++) {
+#pragma unroll
+      for (int rt = 0; rt < RT; rt++)
+        a[s][rt] = *reinterpret_cast<const f4*>(Ls + ((size_t)(q0b + s) * (NB / 16) + rt) * 256);
+#pragma unroll
+      for (int ct = 0; ct < CT; ct++)
+        b[s][ct] = *reinterpret_cast<const f4*>(Wb + ((size_t)(q0b + s) * CTS + ct) * 256);
+      asm volatile("" ::: "memory");
+    }
+    for (int q0 = q0b; q0 < q1b; q0 += D) {
+#pragma unroll
+      for (int s = 0; s < D; s++) {
+#pragma unroll
+        for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+          for (int ct = 0; ct < CT; ct++) {
+            c32[rt][ct] = MFMA32(a[s][rt].x, b[s][ct].x, c32[rt][ct]);
+            c32[rt][ct] = MFMA32(a[s][rt].y, b[s][ct].y, c32[rt][ct]);
+            c32[rt][ct] = MFMA32(a[s][rt].z, b[s][ct].z, c32[rt][ct]);
+            c32[rt][ct] = MFMA32(a[s][rt].w, b[s][ct].w, c32[rt][ct]);
+          }
+        int nx = q0 + s + D;
+        nx = nx < q1b ? nx : q1b - 1;
+#pragma unroll
+        for (int rt = 0; rt < RT; rt++)
+          a[s][rt] = *reinterpret_cast<const f4*>(Ls + ((size_t)nx * (NB / 16) + rt) * 256);
+#pragma unroll
+        for (int ct = 0; ct < CT; ct++)
+          b[s][ct] = *reinterpret_cast<const f4*>(Wb + ((size_t)nx * CTS + ct) * 256);
+        asm volatile("" ::: "memory");
+        if ((s + 1) % CHQ == 0) {
+          // end of an FP32 chunk: fold into the FP64 running sum
+#pragma unroll
+          for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+            for (int ct = 0; ct < CT; ct++) {
+#pragma unroll
+              for (int i = 0; i < 4; i++) acc[rt][ct][i] += (double)c32[rt][ct][i];
+              c32[rt][ct] = (f4){0, 0, 0, 0};
+            }
+        }
+      }
+    }
+  }
+  // partial sums into this wave row's rows of Rl (the FP32 output layout:
+  // element i of lane l is row 4(l/16) + i of the tile), then the first wave
+  // row's rows gather them
+#pragma unroll
+  for (int rt = 0; rt < RT; rt++) {
+    const int rowl = wr * RW + rt * 16;
+    const int ks = rowl / 4 + lane / 16;
+#pragma unroll
+    for (int ct = 0; ct < CT; ct++)
+#pragma unroll
+      for (int i = 0; i < 4; i++)
+        Rl[((size_t)(ks / 2) * CTS + wc * CT + ct) * 128 + (i * 16 + lane % 16) * 2 + (ks % 2)] =
+            xs * xv[rt][ct][i] - acc[rt][ct][i];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < RW * C; i += 64 * WR * WC) {
+    double v = Rl[i];
+#pragma unroll
+    for (int w = 1; w < WR; w++) {
+      v += Rl[(size_t)w * RW * C + i];
+      Rl[(size_t)w * RW * C + i] = 0.0;
+    }
+    Rl[i] = v;
+  }
+  __syncthreads();
+  // W_k = inv(L_kk) R_k in FP64 and both stores, as in k_trsm_mixed
+  d4 w64[RT][CT];
+#pragma unroll
+  for (int a = 0; a < RT; a++)
+#pragma unroll
+    for (int b = 0; b < CT; b++) w64[a][b] = (d4){0, 0, 0, 0};
+  const double* __restrict__ Li = J.LinvP + (size_t)k * NB * NB + (size_t)(wr * RT) * 128 + lane * 2;
+  const int kp_end = (wr * RW + RW) / 8;
+  for (int kp = 0; kp < kp_end; kp++) {
+    d2 a[RT], b[CT];
+#pragma unroll
+    for (int rt = 0; rt < RT; rt++)
+      a[rt] = *reinterpret_cast<const d2*>(Li + ((size_t)kp * (NB / 16) + rt) * 128);
+#pragma unroll
+    for (int ct = 0; ct < CT; ct++)
+      b[ct] = *reinterpret_cast<const d2*>(&Rl[((size_t)kp * CTS + wc * CT + ct) * 128 + lane * 2]);
+#pragma unroll
+    for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+      for (int ct = 0; ct < CT; ct++) {
+        w64[rt][ct] = MFMA64(a[rt].x, b[ct].x, w64[rt][ct]);
+        w64[rt][ct] = MFMA64(a[rt].y, b[ct].y, w64[rt][ct]);
+      }
+  }
+#pragma unroll
+  for (int rt = 0; rt < RT; rt++) {
+    const int64_t row0 = (int64_t)k * NB + wr * RW + rt * 16;
+    const int64_t ks0 = row0 / 4;
+#pragma unroll
+    for (int ct = 0; ct < CT; ct++) {
+#pragma unroll
+      for (int i = 0; i < 4; i += 2)
+        *reinterpret_cast<d2*>(Wslab + ((size_t)((ks0 + i) / 2) * CTS + wc * CT + ct) * 128 + lane * 2) =
+            (d2){w64[rt][ct][i], w64[rt][ct][i + 1]};
+      *reinterpret_cast<f4*>(W32slab + ((size_t)(row0 / 16) * CTS + wc * CT + ct) * 256 + lane * 4) =
+          (f4){(float)w64[rt][ct][0], (float)w64[rt][ct][1], (float)w64[rt][ct][2],
+               (float)w64[rt][ct][3]};
+    }
+  }
+}
+
+
 hipError_t launch_trsm_mixed(const JobTable& tab, int64_t nslabs, int C, hipStream_t st) {
+  bool last = false;  // some job of the table leaves its last block to k_trsm_mixed_last
+  for (int i = 0; i < tab.njobs; i++) last = last || mixed_last_block_split(tab.j[i].n, tab.j[i].K, NB / 4);
   switch (C) {
-    case 32: k_trsm_mixed<32, 4, 2, 4, FP32_CHUNK_QUADS><<<(unsigned)nslabs, 512, 0, st>>>(tab); break;
-    case 64: k_trsm_mixed<64, 4, 2, 4, FP32_CHUNK_QUADS><<<(unsigned)nslabs, 512, 0, st>>>(tab); break;
+    case 32:
+      k_trsm_mixed<32, 4, 2, 4, FP32_CHUNK_QUADS><<<(unsigned)nslabs, 512, 0, st>>>(tab);
+      if (last) k_trsm_mixed_last<32, 4, 2, 4, FP32_CHUNK_QUADS><<<(unsigned)nslabs, 512, 0, st>>>(tab);
+      break;
+    case 64:
+      k_trsm_mixed<64, 4, 2, 4, FP32_CHUNK_QUADS><<<(unsigned)nslabs, 512, 0, st>>>(tab);
+      if (last) k_trsm_mixed_last<64, 4, 2, 4, FP32_CHUNK_QUADS><<<(unsigned)nslabs, 512, 0, st>>>(tab);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
