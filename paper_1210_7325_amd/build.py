@@ -3,6 +3,7 @@
   libgls.so     the solver (HIP kernels for gfx950 + the C ABI of include/gls.h)
   libglsgen.so  the synthetic-input generator (host C, OpenMP)
   libglsgen_dev.so  its device twin (HIP), for inputs generated in HBM
+  tests/c_abi/gls_c_check  a C program using only include/gls.h (test)
 
 Run `python -m paper_1210_7325_amd.build` or call build_all().
 """
@@ -98,10 +99,26 @@ def build_gen_dev() -> str:
     return os.path.join(PKG, "libglsgen_dev.so")
 
 
+def build_c_check() -> str:
+    """The C program of tests/c_abi that drives libgls through its C ABI only
+    (test infrastructure; found next to its source, libgls.so via rpath)."""
+    src = os.path.join(ROOT, "tests", "c_abi", "gls_c_check.c")
+    out = os.path.join(ROOT, "tests", "c_abi", "gls_c_check")
+    cc = shutil.which("gcc") or "cc"
+    rocm = os.path.dirname(os.path.dirname(os.path.realpath(HIPCC)))
+    tmp = out + ".tmp"
+    _run([cc, "-O2", "-std=c11", "-D__HIP_PLATFORM_AMD__", f"-I{rocm}/include", f"-I{INCLUDE}", src,
+          "-o", tmp, f"-L{PKG}", "-lgls", f"-L{rocm}/lib", "-lamdhip64", "-lm",
+          "-Wl,-rpath,$ORIGIN/../../paper_1210_7325_amd", f"-Wl,-rpath,{rocm}/lib"])
+    os.replace(tmp, out)
+    return out
+
+
 def build_all() -> None:
     build_gen()
     build_gen_dev()
     build_gls()
+    build_c_check()
 
 
 if __name__ == "__main__":
