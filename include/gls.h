@@ -123,10 +123,11 @@ int gls_fork(gls_handle h, void* stream, gls_handle* out);
 int gls_set_stream(gls_handle h, void* stream);
 
 /* Device bytes a handle holds for a cohort of n individuals, p_L fixed
- * columns, t phenotypes and blocks of up to max_cols genotype columns in
- * precision prec (factor, fixed part and workspace; the transient buffer
- * of gls_factor is counted too).  Used for admission by memory footprint. */
-size_t gls_footprint_bytes(int64_t n, int64_t p_L, int64_t t, int64_t max_cols,
+ * columns, p_R genotype columns per problem, t phenotypes and blocks of up
+ * to max_nsnp problems in precision prec (factor, fixed part and workspace;
+ * the transient buffer of gls_factor is counted too).  Used for admission
+ * by memory footprint.  0 for invalid sizes. */
+size_t gls_footprint_bytes(int64_t n, int64_t p_L, int64_t p_R, int64_t t, int64_t max_nsnp,
                            int prec);
 
 /* Order of the first non-positive leading minor found by gls_factor, 0 if

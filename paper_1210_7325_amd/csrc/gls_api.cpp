@@ -309,8 +309,10 @@ const char* gls_strerror(int code) {
   }
 }
 
-size_t gls_footprint_bytes(int64_t n, int64_t p_L, int64_t t, int64_t max_cols, int prec) {
-  if (n < 1 || p_L < 0 || t < 0 || max_cols < 0) return 0;
+size_t gls_footprint_bytes(int64_t n, int64_t p_L, int64_t p_R, int64_t t, int64_t max_nsnp,
+                           int prec) {
+  if (n < 1 || p_L < 0 || p_R < 1 || t < 0 || max_nsnp < 0) return 0;
+  const int64_t max_cols = max_nsnp * p_R;
   const int K = (int)((n + NB - 1) / NB);
   const size_t n_pad = (size_t)K * NB;
   size_t b = 0;

@@ -79,7 +79,7 @@ def lib() -> ctypes.CDLL:
             "gls_free": (None, [_p]),
             "gls_fork": (_int, [_p, _p, ctypes.POINTER(_p)]),
             "gls_set_stream": (_int, [_p, _p]),
-            "gls_footprint_bytes": (ctypes.c_size_t, [_i64, _i64, _i64, _i64, _int]),
+            "gls_footprint_bytes": (ctypes.c_size_t, [_i64, _i64, _i64, _i64, _i64, _int]),
             "gls_last_info": (_int, [_p]),
             "gls_strerror": (ctypes.c_char_p, [_int]),
             "gls_copy_factor": (_int, [_p, _p, _i64]),
@@ -153,8 +153,8 @@ def gls_set_stream(h, stream) -> int:
     return lib().gls_set_stream(h, stream)
 
 
-def gls_footprint_bytes(n, p_L, t, max_cols, prec) -> int:
-    return int(lib().gls_footprint_bytes(n, p_L, t, max_cols, prec))
+def gls_footprint_bytes(n, p_L, p_R, t, max_nsnp, prec) -> int:
+    return int(lib().gls_footprint_bytes(n, p_L, p_R, t, max_nsnp, prec))
 
 
 def gls_last_info(h) -> int:

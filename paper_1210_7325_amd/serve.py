@@ -283,7 +283,7 @@ class GpuExecutor(Executor):
     def footprint(self, job: Job) -> int:
         p = self.gls.PRECISIONS[self.precision]
         blk = job.max_block or job.block or job_block(job.n)
-        b = self.gls.gls_footprint_bytes(job.n, job.p_L, 1, blk, p)
+        b = self.gls.gls_footprint_bytes(job.n, job.p_L, 1, 1, blk, p)
         b += job.n * blk                                       # genotype block
         b += job.m * job.p * 8 + job.m * 4                     # b and info
         b += job.n * job.n * 8                                 # M while factoring

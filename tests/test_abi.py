@@ -78,9 +78,12 @@ def test_footprint_arithmetic():
               + npad * npad * 8 + K * 128 * 128 * 8
               + npad * (pL + t) * 8 + (pL + t) ** 2 * 8
               + npad * 4096 * 8)
-    assert L.gls_footprint_bytes(n, pL, t, cols, 0) == expect
-    assert L.gls_footprint_bytes(n, pL, t, cols, 1) > expect
-    assert L.gls_footprint_bytes(0, pL, t, cols, 0) == 0
+    assert L.gls_footprint_bytes(n, pL, 1, t, cols, 0) == expect
+    assert L.gls_footprint_bytes(n, pL, 1, t, cols, 1) > expect
+    assert L.gls_footprint_bytes(0, pL, 1, t, cols, 0) == 0
     # monotone in every size
-    assert L.gls_footprint_bytes(2 * n, pL, t, cols, 0) > expect
-    assert L.gls_footprint_bytes(n, pL, t, 2 * cols, 0) > expect
+    assert L.gls_footprint_bytes(2 * n, pL, 1, t, cols, 0) > expect
+    assert L.gls_footprint_bytes(n, pL, 1, t, 2 * cols, 0) > expect
+    # p_R genotype columns per problem: the workspace of nsnp p_R columns
+    assert L.gls_footprint_bytes(n, pL, 2, t, cols // 2, 0) == expect
+    assert L.gls_footprint_bytes(n, pL, 0, t, cols, 0) == 0
