@@ -189,6 +189,28 @@ def test_slab_width_choice_is_bitwise_neutral(G, prec):
     c.free()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32_refine"])
+@pytest.mark.parametrize("n,pad,offset", [(1000, 5, 0), (1000, 16, 3), (203, 13, 1)])
+def test_genotypes_with_a_padded_leading_dimension(G, prec, n, pad, offset):
+    """X_R inside a larger column-major array (ldxr = n + pad, the block
+    starting `offset` rows down): the same bits as the packed array.  Covers
+    the aligned and the unaligned loads of the centering pre-pass."""
+    say("padded ld", prec, n, pad, offset)
+    from paper_1210_7325_amd import gls
+    w, M, XL, Y, XR = small_problem(n, m=150)
+    c = gls.Cohort(to_dev(M), precision=prec).whiten_fixed(to_dev(XL), to_dev(Y), intercept_col=0)
+    ref, _ = c.solve_block(to_dev(XR))
+    big = np.full((n + pad, XR.shape[1]), 7, dtype=np.int8)
+    big[offset:offset + n] = XR
+    dbig = to_dev(big)
+    view = dbig[offset:offset + n]                 # stride(1) = n + pad
+    assert view.stride(0) == 1 and view.stride(1) == n + pad
+    B, info = c.solve_block(view)
+    assert np.array_equal(B.cpu().numpy(), ref.cpu().numpy())
+    assert np.all(info.cpu().numpy() == 0)
+    c.free()
+
+
 def test_multi_cohort_launch_equals_single(G):
     say("multi")
     from paper_1210_7325_amd import gls
