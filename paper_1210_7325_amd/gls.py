@@ -7,7 +7,7 @@ fails loudly otherwise, there is no fallback.
 
 Two levels:
   * the raw entry points, same names and arguments as the C functions
-    (pointers and streams as Python ints), raising GLSError on failure;
+    (pointers and streams as Python ints), returning the C return codes;
   * Cohort, a small convenience class over torch tensors.
 
 Matrices are column-major: a (rows, cols) tensor with stride(0) == 1; other
@@ -385,6 +385,8 @@ def solve_multi(items, stream=None):
     kernel on `stream`."""
     works = []
     for c, XR, p_R, B, info in items:
+        # no layout copies here: the launch reads the caller's arrays as they are
+        assert XR.stride(0) == 1 and B.is_contiguous(), "X_R column-major, B contiguous"
         works.append(gls_work(c.h, XR.shape[1] // p_R, p_R, XR.data_ptr(), _ld(XR), B.data_ptr(),
                               c.p_L + p_R, info.data_ptr() if info is not None else None))
     _chk(gls_solve_multi(works, _stream_ptr(stream)), "gls_solve_multi")
