@@ -107,7 +107,7 @@ int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 size_t strips_count(int K) { return (size_t)K * (size_t)(K - 1) / 2 * (size_t)NB * NB; }
 
 int ensure_workspace(gls_handle h, int64_t ncols) {
-  const int64_t need = round_up(std::max<int64_t>(ncols, 1), 64);
+  const int64_t need = round_up(std::max<int64_t>(ncols, 1), MAX_C);
   if (need <= h->Wcols) return GLS_OK;
   HIPCHK(hipStreamSynchronize(h->stream));
   dfree(h->W);
@@ -321,11 +321,11 @@ size_t gls_footprint_bytes(int64_t n, int64_t p_L, int64_t p_R, int64_t t, int64
   b += n_pad * n_pad * 8 + (size_t)K * NB * NB * 8;  // factorization work (transient)
   const size_t w = (size_t)(p_L + t);
   b += n_pad * w * 8 + (w * w) * 8;  // fixed part
-  b += n_pad * (size_t)round_up(std::max<int64_t>(max_cols, 1), 64) * 8;  // workspace
+  b += n_pad * (size_t)round_up(std::max<int64_t>(max_cols, 1), MAX_C) * 8;  // workspace
   if (prec == GLS_FP32_REFINE) {
     b += strips_count(K) * 4;                                   // FP32 strips
     b += n_pad * w * 8;                                         // Z
-    const size_t cols = (size_t)round_up(std::max<int64_t>(max_cols, 1), 64);
+    const size_t cols = (size_t)round_up(std::max<int64_t>(max_cols, 1), MAX_C);
     b += n_pad * cols * 4 + cols * 8 + cols * (MAXP + MAXT) * 8;  // W32, shift, XZ
   }
   return b;
@@ -569,8 +569,9 @@ int gls_whiten_block(gls_handle h, int64_t ncols, const int8_t* X, int64_t ldx, 
 
 int gls_set_slab_cols(gls_handle h, int cols) {
   if (!h) return -1;
-  if (cols != 0 && cols != 16 && cols != 32 && cols != 64) return -2;
+  if (cols != 0 && cols != 16 && cols != 32 && cols != 64 && cols != 128) return -2;
   if (h->c->prec == GLS_FP32_REFINE && cols == 16) return GLS_E_UNSUPPORTED;
+  if (h->c->prec != GLS_FP32_REFINE && cols == 128) return GLS_E_UNSUPPORTED;
   h->C = cols;
   return GLS_OK;
 }

@@ -53,16 +53,34 @@ __global__ __launch_bounds__(64 * WR * WC) void k_trsm(const JobTable tab) {
   // lie in the first wave row's tile
   const int Kmain = last_block_split(n, K, RW) ? K - 1 : K;
   for (int k = 0; k < Kmain; k++) {
-    // this block's right-hand side, loaded early (consumed after the GEMM)
-    double xv[RT][CT][4];
+    // this block's right-hand side, loaded early and held as loaded (it is
+    // consumed after the GEMM).  When the wave's tile lies inside the matrix
+    // (all but the last row block and the last slab) the loads are plain, so
+    // they all issue before the first wait; a guarded load is a branch with
+    // a wait of its own.
+    TIn xv[RT][CT][4];
+    if ((int64_t)k * NB + wr * RW + RW <= n && col_base + CW <= ncols) {
 #pragma unroll
-    for (int rt = 0; rt < RT; rt++)
+      for (int ct = 0; ct < CT; ct++) {
+        const TIn* __restrict__ xc =
+            X + (col_base + ct * 16 + lane % 16) * ldx + (int64_t)k * NB + wr * RW + lane / 16;
 #pragma unroll
-      for (int ct = 0; ct < CT; ct++)
+        for (int rt = 0; rt < RT; rt++)
 #pragma unroll
-        for (int i = 0; i < 4; i++)
-          xv[rt][ct][i] = load_x<TIn>(X, ldx, (int64_t)k * NB + wr * RW + rt * 16 + lane / 16 + 4 * i,
-                                      col_base + ct * 16 + lane % 16, n, ncols);
+          for (int i = 0; i < 4; i++) xv[rt][ct][i] = xc[rt * 16 + 4 * i];
+      }
+    } else {
+#pragma unroll
+      for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+        for (int ct = 0; ct < CT; ct++)
+#pragma unroll
+          for (int i = 0; i < 4; i++) {
+            const int64_t row = (int64_t)k * NB + wr * RW + rt * 16 + lane / 16 + 4 * i;
+            const int64_t col = col_base + ct * 16 + lane % 16;
+            xv[rt][ct][i] = (row < n && col < ncols) ? X[col * ldx + row] : (TIn)0;
+          }
+    }
 
     d4 acc[RT][CT];
 #pragma unroll
@@ -121,7 +139,7 @@ __global__ __launch_bounds__(64 * WR * WC) void k_trsm(const JobTable tab) {
         for (int i = 0; i < 4; i += 2) {
           const int kp = (rowl / 4 + i) / 2;
           *reinterpret_cast<d2*>(&Rl[((size_t)kp * CTS + wc * CT + ct) * 128 + lane * 2]) =
-              (d2){xv[rt][ct][i] - acc[rt][ct][i], xv[rt][ct][i + 1] - acc[rt][ct][i + 1]};
+              (d2){(double)xv[rt][ct][i] - acc[rt][ct][i], (double)xv[rt][ct][i + 1] - acc[rt][ct][i + 1]};
         }
       }
     }

@@ -48,19 +48,46 @@ __global__ __launch_bounds__(64 * WR * WC) void k_trsm_mixed(const JobTable tab)
   // the last row block is left to k_trsm_mixed_last when all of its real
   // rows lie in the first wave row's tile
   const int Kmain = mixed_last_block_split(n, K, RW) ? K - 1 : K;
-  for (int k = 0; k < Kmain; k++) {
-    double xv[RT][CT][4];
-#pragma unroll
-    for (int rt = 0; rt < RT; rt++)
+  // The block's right-hand side: genotypes as loaded (0 outside the
+  // matrix) and the shift of each column (0 past the last column); the
+  // centered value is formed where it is consumed.  Loaded before the GEMM,
+  // so that the GEMM hides the latency, unless the wave's tile is so wide
+  // (C = 128) that holding it through the GEMM would spill registers.  When
+  // the wave's tile lies inside the matrix (all but the last row block and
+  // the last slab) the loads are plain, so they all issue before the first
+  // wait; a guarded load is a branch with a wait of its own.
+  constexpr bool late_rhs = C >= 128;
+  auto load_rhs = [&](int k, int8_t (&xv)[RT][CT][4], double (&sc)[CT]) {
+    if ((int64_t)k * NB + wr * RW + RW <= n && col_base + CW <= ncols) {
 #pragma unroll
       for (int ct = 0; ct < CT; ct++) {
         const int64_t col = col_base + ct * 16 + lane % 16;
+        const int8_t* __restrict__ xc = X + col * ldx + (int64_t)k * NB + wr * RW + 4 * (lane / 16);
+        sc[ct] = shift[col];
 #pragma unroll
-        for (int i = 0; i < 4; i++) {
-          const int64_t row = (int64_t)k * NB + wr * RW + rt * 16 + 4 * (lane / 16) + i;
-          xv[rt][ct][i] = (row < n && col < ncols) ? (double)X[col * ldx + row] - shift[col] : 0.0;
-        }
+        for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+          for (int i = 0; i < 4; i++) xv[rt][ct][i] = xc[rt * 16 + i];
       }
+    } else {
+#pragma unroll
+      for (int ct = 0; ct < CT; ct++) {
+        const int64_t col = col_base + ct * 16 + lane % 16;
+        sc[ct] = col < ncols ? shift[col] : 0.0;
+#pragma unroll
+        for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+          for (int i = 0; i < 4; i++) {
+            const int64_t row = (int64_t)k * NB + wr * RW + rt * 16 + 4 * (lane / 16) + i;
+            xv[rt][ct][i] = (row < n && col < ncols) ? X[col * ldx + row] : (int8_t)0;
+          }
+      }
+    }
+  };
+  for (int k = 0; k < Kmain; k++) {
+    int8_t xv[RT][CT][4];
+    double sc[CT];
+    if constexpr (!late_rhs) load_rhs(k, xv, sc);
 
     d4 acc[RT][CT];
     f4 c32[RT][CT];
@@ -132,8 +159,11 @@ __global__ __launch_bounds__(64 * WR * WC) void k_trsm_mixed(const JobTable tab)
       }
     }
 
+    if constexpr (late_rhs) load_rhs(k, xv, sc);
+
     // R_k = (x - s) - acc, to LDS in the FP64 B-operand pair layout: element
-    // (row 4g + i) of the FP32 output goes to k-step (row0/4 + g), lane 16i + l%16
+    // (row 4g + i) of the FP32 output goes to k-step (row0/4 + g), lane 16i + l%16;
+    // padding rows take 0
 #pragma unroll
     for (int rt = 0; rt < RT; rt++) {
       const int rowl = wr * RW + rt * 16;
@@ -141,9 +171,11 @@ __global__ __launch_bounds__(64 * WR * WC) void k_trsm_mixed(const JobTable tab)
 #pragma unroll
       for (int ct = 0; ct < CT; ct++)
 #pragma unroll
-        for (int i = 0; i < 4; i++)
+        for (int i = 0; i < 4; i++) {
+          const bool in = (int64_t)k * NB + rowl + 4 * (lane / 16) + i < n;
           Rl[((size_t)(ks / 2) * CTS + wc * CT + ct) * 128 + (i * 16 + lane % 16) * 2 + (ks % 2)] =
-              xv[rt][ct][i] - acc[rt][ct][i];
+              (in ? (double)xv[rt][ct][i] - sc[ct] : 0.0) - acc[rt][ct][i];
+        }
     }
     __syncthreads();
 
@@ -376,6 +408,10 @@ hipError_t launch_trsm_mixed(const JobTable& tab, int64_t nslabs, int C, hipStre
     case 64:
       k_trsm_mixed<64, 4, 2, 4, FP32_CHUNK_QUADS><<<(unsigned)nslabs, 512, 0, st>>>(tab);
       if (last) k_trsm_mixed_last<64, 4, 2, 4, FP32_CHUNK_QUADS><<<(unsigned)nslabs, 512, 0, st>>>(tab);
+      break;
+    case 128:
+      k_trsm_mixed<128, 4, 2, 2, FP32_CHUNK_QUADS><<<(unsigned)nslabs, 512, 0, st>>>(tab);
+      if (last) k_trsm_mixed_last<128, 4, 2, 2, FP32_CHUNK_QUADS><<<(unsigned)nslabs, 512, 0, st>>>(tab);
       break;
     default: return hipErrorInvalidValue;
   }

@@ -73,6 +73,24 @@ def test_fp32_refine_parity(G, n, pL, pR, t, m, block):
     assert err.max() < TOL_FP32_FORM
 
 
+@pytest.mark.parametrize("n,m,block", [(660, 300, 300), (1000, 700, 333)])
+def test_fp32_refine_wide_slabs(G, n, m, block):
+    """128 genotype columns per work-group (the FP32_REFINE form only): within
+    the bound of the oracle and the same bits as 64.  n = 660 leaves its last
+    row block of 20 rows to the last-block kernel; n = 1000 ends in a partial
+    row block of the main kernel; both blocks end in a partial slab."""
+    say("fp32 form, 128-column slabs", n, m, block)
+    w, M, XL, Y, XR = problem(n, 3, 1, m, seed=n + 1)
+    B, info = run(G, M, XL, Y, XR, 1, block, slab=128)
+    B64, _ = run(G, M, XL, Y, XR, 1, block, slab=64)
+    ref = orc.gls_sequence(M, XL, XR, Y, 1)
+    assert np.all(info == 0)
+    err = orc.relative_error(B, ref)
+    say("max rel err", err.max())
+    assert err.max() < TOL_FP32_FORM
+    assert np.array_equal(B, B64)
+
+
 def test_fp32_refine_stress_conditioning(G):
     """q = n/4, h = 0.99: kappa(M) ~ 800 (the workloads have kappa ~ 4-10).
     The FP32-rounded operands of the off-diagonal products leave an error

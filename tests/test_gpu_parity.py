@@ -177,7 +177,7 @@ def test_slab_width_choice_is_bitwise_neutral(G, prec):
     w, M, XL, Y, XR = small_problem(700, m=20000)
     c = gls.Cohort(to_dev(M), precision=prec).whiten_fixed(to_dev(XL), to_dev(Y), intercept_col=0)
     dXR = to_dev(XR)
-    widths = (32, 64) if prec == "fp32_refine" else (16, 32, 64)
+    widths = (32, 64, 128) if prec == "fp32_refine" else (16, 32, 64)
     for m in (100, 5000, 20000):
         c.set_slab_cols(0)
         ref, _ = c.solve_block(dXR[:, :m])
