@@ -56,10 +56,11 @@ def parse():
     ap.add_argument("--block", type=int, default=None, help="SNPs per solve call (default 4096)")
     ap.add_argument("--streams", type=int, default=1)
     ap.add_argument("--batch", type=int, default=None,
-                    help="blocks whitened per launch (default: 4 / p_R)")
+                    help="blocks whitened per launch (default: enough columns for one slab of the "
+                         "form's widest width per CU: 64 in FP64, 128 in FP32_REFINE)")
     ap.add_argument("--slab-cols", type=int, default=0,
-                    help="columns per work-group of the solve: 16, 32, 64, or 0 to let the library "
-                         "choose per launch")
+                    help="columns per work-group of the solve: 16, 32, 64 (128 in FP32_REFINE), "
+                         "or 0 to let the library choose per launch")
     ap.add_argument("--forms", default="fp64,fp32_refine",
                     help="precisions to time, the first is the headline")
     ap.add_argument("--parity-sample", type=int, default=1000,
@@ -579,9 +580,17 @@ def main():
     w = WORKLOADS[args.workload]
     m = args.m or w.m
     block = args.block or w.block
-    batch = args.batch or max(1, 4 // w.p_R)
     forms = args.forms.split(",")
     torch.cuda.set_device(0)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+
+    def batch_for(prec):
+        # blocks per launch: one slab of the widest width per CU
+        if args.batch:
+            return args.batch
+        widest = args.slab_cols or (128 if prec == "fp32_refine" else 64)
+        return max(1, cus * widest // (block * w.p_R))
+    batch = batch_for(forms[0])
 
     t0 = time.time()
     M = dg.make_M(w)
@@ -596,8 +605,8 @@ def main():
     results, outs = {}, {}
     for prec in forms:
         Bout = torch.empty((m, w.t, w.p), dtype=torch.float64, device="cuda")
-        results[prec] = time_form(gls, torch, args, w, m, block, batch, dM, dXL, dY, dXR, Bout,
-                                  info, prec)
+        results[prec] = time_form(gls, torch, args, w, m, block, batch_for(prec), dM, dXL, dY, dXR,
+                                  Bout, info, prec)
         outs[prec] = Bout.cpu().numpy()
         del Bout
     del dXR
@@ -650,7 +659,7 @@ def main():
             "speedup_vs_" + forms[0]: round(r["value"] / head["value"], 3),
             "trsm_tflops": round(r["trsm_tflops"], 3), "trsm_peak": r["peak"],
             "trsm_frac": round(r["trsm_tflops"] / r["peak"], 4),
-            "trsm_avg_launch_ms": round(r["trsm_avg_ms"], 4),
+            "trsm_avg_launch_ms": round(r["trsm_avg_ms"], 4), "blocks_per_launch": batch_for(prec),
             **parity.get(prec, {}),
         }
     out = {

@@ -225,21 +225,28 @@ struct TimedScope {
 // compute unit (measured at n = 10^4, FP64: 576 to 4,096 columns in 9.9 ms
 // with 16-column slabs against 22.9 ms with 64; 8,192 columns in 16.4 ms
 // with 32 against 23.3 ms), while launches that fill the chip are fastest
-// with 64.  The FP32_REFINE kernel has no 16-column form.  A width set on
-// the handle overrides the choice.
+// with the widest: 64 in FP64, 128 in FP32_REFINE (measured at n = 10^4:
+// 32,768 columns in 32.2 ms with 128-column slabs against 34.6 ms with 64).
+// The FP32_REFINE kernel has no 16-column form, the FP64 one no 128-column
+// form.  A width set on the handle overrides the choice.
+int widest_slab(const gls_handle h) { return h->c->prec == GLS_FP32_REFINE ? MAX_C : DEFAULT_C; }
+
 int slab_cols_for(const gls_work* items, int64_t count) {
   const gls_handle h = items[0].h;
   if (h->C != 0) return h->C;
-  int64_t s16 = 0, s32 = 0;
+  int64_t s16 = 0, s32 = 0, s64 = 0;
   for (int64_t i = 0; i < count; i++) {
     const int64_t ncols = items[i].nsnp * items[i].p_R;
     s16 += (ncols + 15) / 16;
     s32 += (ncols + 31) / 32;
+    s64 += (ncols + 63) / 64;
   }
   const int64_t cus = h->c->cus;
-  if (h->c->prec != GLS_FP32_REFINE && s16 <= cus) return 16;
+  const bool fp32 = h->c->prec == GLS_FP32_REFINE;
+  if (!fp32 && s16 <= cus) return 16;
   if (s32 <= cus) return 32;
-  return 64;
+  if (!fp32 || s64 <= cus) return 64;
+  return 128;
 }
 
 // Launch the kernels of up to MAX_INLINE_JOBS checked work items (same slab
@@ -630,7 +637,7 @@ int gls_solve_stream(gls_handle h, int64_t snp_begin, int64_t snp_end, int64_t b
   // I/O happens per block of `block` problems; the device solves
   // superblocks of `group` consecutive blocks so that one launch has at
   // least one slab per CU (results do not depend on the grouping)
-  const int64_t target_cols = h->c->cus * (int64_t)(h->C ? h->C : DEFAULT_C);
+  const int64_t target_cols = h->c->cus * (int64_t)(h->C ? h->C : widest_slab(h));
   const int64_t group = std::max<int64_t>(1, (target_cols + block * p_R - 1) / (block * p_R));
   const int64_t sbk = group * block;  // problems per superblock
   const int64_t cols = sbk * p_R;

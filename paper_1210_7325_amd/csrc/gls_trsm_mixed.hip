@@ -10,6 +10,119 @@ __host__ __device__ inline bool mixed_last_block_split(int64_t n, int K, int RW)
   return K > 1 && n - (int64_t)(K - 1) * NB <= RW;
 }
 
+// vmcnt <= N with lgkmcnt = 0 (gfx9 s_waitcnt encoding; expcnt left free)
+template <int N>
+__device__ __forceinline__ void wait_vm_lgkm0() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | ((N >> 4) << 14));
+}
+
+// One 1 KB chunk (64 lanes x 16 bytes) from global memory straight into LDS
+// at dst + 16 * lane (global_load_lds_dwordx4; dst is wave-uniform).
+__device__ __forceinline__ void chunk_to_lds(const float* src, float* dst) {
+  __builtin_amdgcn_global_load_lds((const void*)src, (__attribute__((address_space(3))) void*)dst, 16,
+                                   0, 0);
+}
+
+// The off-diagonal sum acc = sum_{j<k} L_kj W_j of the mixed solve for one
+// row block, with the operands staged through LDS: a stage is G k-step quads,
+// i.e. G (NB/16 + C/16) chunks of 1 KB (the L32 strip tiles of all NB rows
+// and the W32 tiles of all C columns), copied by the work-group's waves
+// straight into one of S LDS slots, S - 1 stages ahead.  Every wave then
+// reads its own tiles from LDS: each operand byte crosses the L1 cache once
+// per work-group, and the stages in flight cost no registers.  A wave waits
+// for its own copies of a stage (vmcnt), then the barrier makes all of them
+// visible and frees the slot read in the previous stage, which the next
+// copy then fills.  FP32 accumulation over one quad, then the FP64 running
+// sum, as in the register-ring form.
+template <int C, int G>
+constexpr int staged_ring_floats(int S) { return S * G * (NB / 16 + C / 16) * 256; }
+
+template <int C, int WR, int WC, int G, int S>
+__device__ __forceinline__ void gemm_staged(const float* __restrict__ Lk, const float* __restrict__ W32slab,
+                                            int nq, float* __restrict__ ring_base,
+                                            d4 (&acc)[NB / WR / 16][C / WC / 16]) {
+  constexpr int RT = NB / WR / 16, CT = C / WC / 16, CTS = C / 16, NQB = NB / 16;
+  constexpr int NW = WR * WC;
+  constexpr int CL = G * NQB;          // chunks of L per stage
+  constexpr int CPS = G * (NQB + CTS); // chunks per stage
+  constexpr int LPW_HI = (CPS + NW - 1) / NW, LPW_LO = CPS / NW;
+  float(*ring)[CPS * 256] = reinterpret_cast<float(*)[CPS * 256]>(ring_base);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x % 64;
+  const int wr = wave / WC, wc = wave % WC;
+  const int nst = nq / G;
+  // this wave's copies of stage st into slot sl (chunk c = wave + i NW)
+  auto issue = [&](int st, int sl) {
+#pragma unroll
+    for (int i = 0; i < LPW_HI; i++) {
+      const int c = wave + i * NW;
+      if (c < CPS) {
+        const float* src = c < CL ? Lk + ((size_t)st * CL + c) * 256 + lane * 4
+                                  : W32slab + ((size_t)st * G * CTS + (c - CL)) * 256 + lane * 4;
+        chunk_to_lds(src, &ring[sl][c * 256]);
+      }
+    }
+  };
+#pragma unroll
+  for (int sl = 0; sl < S - 1; sl++) issue(sl < nst ? sl : nst - 1, sl);
+  f4 c32[RT][CT];
+#pragma unroll
+  for (int a = 0; a < RT; a++)
+#pragma unroll
+    for (int b = 0; b < CT; b++) c32[a][b] = (f4){0, 0, 0, 0};
+  for (int st = 0; st < nst; st++) {
+    // stage st is in LDS for every wave; every wave is done with slot (st-1)%S
+    if (LPW_HI == LPW_LO || wave < CPS % NW)
+      wait_vm_lgkm0<(S - 2) * LPW_HI>();
+    else
+      wait_vm_lgkm0<(S - 2) * LPW_LO>();
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    {
+      // refill the freed slot with stage st + S - 1 (clamped: the tail
+      // copies are never read)
+      const int nx = st + S - 1;
+      issue(nx < nst ? nx : nst - 1, nx % S);
+    }
+    const float* __restrict__ slot = ring[st % S];
+#pragma unroll
+    for (int g = 0; g < G; g++) {
+      f4 a[RT], b[CT];
+#pragma unroll
+      for (int rt = 0; rt < RT; rt++)
+        a[rt] = *reinterpret_cast<const f4*>(slot + (g * NQB + wr * RT + rt) * 256 + lane * 4);
+#pragma unroll
+      for (int ct = 0; ct < CT; ct++)
+        b[ct] = *reinterpret_cast<const f4*>(slot + (CL + g * CTS + wc * CT + ct) * 256 + lane * 4);
+#pragma unroll
+      for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+        for (int ct = 0; ct < CT; ct++) {
+          c32[rt][ct] = MFMA32(a[rt].x, b[ct].x, c32[rt][ct]);
+          c32[rt][ct] = MFMA32(a[rt].y, b[ct].y, c32[rt][ct]);
+          c32[rt][ct] = MFMA32(a[rt].z, b[ct].z, c32[rt][ct]);
+          c32[rt][ct] = MFMA32(a[rt].w, b[ct].w, c32[rt][ct]);
+        }
+#pragma unroll
+      for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+        for (int ct = 0; ct < CT; ct++) {
+#pragma unroll
+          for (int i = 0; i < 4; i++) acc[rt][ct][i] += (double)c32[rt][ct][i];
+          c32[rt][ct] = (f4){0, 0, 0, 0};
+        }
+    }
+    asm volatile("" ::: "memory");
+  }
+  // the ring shares its LDS with the right-hand side staged next: the tail
+  // copies land and every wave is done reading before that is written
+  wait_vm_lgkm0<0>();
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
 // Mixed-precision blocked lower solve W = L^{-1}(X - 1 s^T): as k_trsm, but
 // each off-diagonal product L_kj W_j uses FP32-rounded operands on FP32 MFMA
 // (v_mfma_f32_16x16x4f32) with FP32 accumulation over one chunk of CHQ
@@ -18,14 +131,22 @@ __host__ __device__ inline bool mixed_last_block_split(int64_t n, int K, int RW)
 // step inv(L_kk) R_k stays FP64.  Both W (FP64, for the assembly) and an
 // FP32 copy (quad layout, for later trailing products) are stored.
 // The FP32 output layout is lane l, element i -> row 4(l/16) + i.
-template <int C, int WR, int WC, int D, int CHQ>
+// Operands of the off-diagonal products: S = 0, a register ring of D quads
+// per wave (each wave loads its own tiles); S > 0, stages of G quads copied
+// through S LDS slots (gemm_staged), which lets one work-group take 128
+// columns (a 32 x 64 tile per wave) and halves the L traffic per column.
+template <int C, int WR, int WC, int D, int CHQ, int G = 1, int S = 0>
 __global__ __launch_bounds__(64 * WR * WC) void k_trsm_mixed(const JobTable tab) {
   constexpr int RW = NB / WR, RT = RW / 16;
   constexpr int CW = C / WC, CT = CW / 16;
   constexpr int CTS = C / 16;
   constexpr int NQB = NB / 16;  // k-step quads per row block
   static_assert(NQB % CHQ == 0 && (CHQ % D == 0 || D % CHQ == 0), "chunking");
-  __shared__ __attribute__((aligned(16))) double Rl[NB * C];
+  static_assert(S == 0 || (CHQ == 1 && NQB % G == 0 && S >= 2), "staging");
+  // R_k for the diagonal step; with staged operands the same LDS holds the
+  // stage ring during the GEMM
+  constexpr int RL_DOUBLES = NB * C > staged_ring_floats<C, G>(S) / 2 ? NB * C : staged_ring_floats<C, G>(S) / 2;
+  __shared__ __attribute__((aligned(16))) double Rl[RL_DOUBLES];
 
   int jb = 0;
   while (jb + 1 < tab.njobs && (int64_t)blockIdx.x >= tab.j[jb + 1].slab0) jb++;
@@ -48,16 +169,16 @@ __global__ __launch_bounds__(64 * WR * WC) void k_trsm_mixed(const JobTable tab)
   // the last row block is left to k_trsm_mixed_last when all of its real
   // rows lie in the first wave row's tile
   const int Kmain = mixed_last_block_split(n, K, RW) ? K - 1 : K;
-  // The block's right-hand side: genotypes as loaded (0 outside the
-  // matrix) and the shift of each column (0 past the last column); the
-  // centered value is formed where it is consumed.  Loaded before the GEMM,
-  // so that the GEMM hides the latency, unless the wave's tile is so wide
-  // (C = 128) that holding it through the GEMM would spill registers.  When
-  // the wave's tile lies inside the matrix (all but the last row block and
-  // the last slab) the loads are plain, so they all issue before the first
-  // wait; a guarded load is a branch with a wait of its own.
-  constexpr bool late_rhs = C >= 128;
-  auto load_rhs = [&](int k, int8_t (&xv)[RT][CT][4], double (&sc)[CT]) {
+  for (int k = 0; k < Kmain; k++) {
+    // The block's right-hand side, loaded before the GEMM so that the GEMM
+    // hides the latency: genotypes as loaded (0 outside the matrix) and the
+    // shift of each column (0 past the last column); the centered value is
+    // formed where it is consumed.  When the wave's tile lies inside the
+    // matrix (all but the last row block and the last slab) the loads are
+    // plain, so they all issue before the first wait; a guarded load is a
+    // branch with a wait of its own.
+    int8_t xv[RT][CT][4];
+    double sc[CT];
     if ((int64_t)k * NB + wr * RW + RW <= n && col_base + CW <= ncols) {
 #pragma unroll
       for (int ct = 0; ct < CT; ct++) {
@@ -83,11 +204,6 @@ __global__ __launch_bounds__(64 * WR * WC) void k_trsm_mixed(const JobTable tab)
           }
       }
     }
-  };
-  for (int k = 0; k < Kmain; k++) {
-    int8_t xv[RT][CT][4];
-    double sc[CT];
-    if constexpr (!late_rhs) load_rhs(k, xv, sc);
 
     d4 acc[RT][CT];
     f4 c32[RT][CT];
@@ -99,10 +215,13 @@ __global__ __launch_bounds__(64 * WR * WC) void k_trsm_mixed(const JobTable tab)
         c32[a][b] = (f4){0, 0, 0, 0};
       }
 
-    const float* __restrict__ Ls = L32 + strip_offset(k) + (size_t)(wr * RT) * 256 + lane * 4;
-    const float* __restrict__ Wb = W32slab + (size_t)(wc * CT) * 256 + lane * 4;
     const int nq = k * NQB;
-    if (nq > 0) {
+    if constexpr (S > 0) {
+      if (nq > 0) gemm_staged<C, WR, WC, G, S>(L32 + strip_offset(k), W32slab, nq, reinterpret_cast<float*>(Rl), acc);
+    } else if (nq > 0) {
+      // register ring: D quads in flight, each wave loading its own tiles
+      const float* __restrict__ Ls = L32 + strip_offset(k) + (size_t)(wr * RT) * 256 + lane * 4;
+      const float* __restrict__ Wb = W32slab + (size_t)(wc * CT) * 256 + lane * 4;
       f4 a[D][RT], b[D][CT];
 #pragma unroll
       for (int s = 0; s < D; s++) {
@@ -158,8 +277,6 @@ __global__ __launch_bounds__(64 * WR * WC) void k_trsm_mixed(const JobTable tab)
         }
       }
     }
-
-    if constexpr (late_rhs) load_rhs(k, xv, sc);
 
     // R_k = (x - s) - acc, to LDS in the FP64 B-operand pair layout: element
     // (row 4g + i) of the FP32 output goes to k-step (row0/4 + g), lane 16i + l%16;
@@ -406,11 +523,11 @@ hipError_t launch_trsm_mixed(const JobTable& tab, int64_t nslabs, int C, hipStre
       if (last) k_trsm_mixed_last<32, 4, 2, 4, FP32_CHUNK_QUADS><<<(unsigned)nslabs, 512, 0, st>>>(tab);
       break;
     case 64:
-      k_trsm_mixed<64, 4, 2, 4, FP32_CHUNK_QUADS><<<(unsigned)nslabs, 512, 0, st>>>(tab);
+      k_trsm_mixed<64, 4, 2, 4, FP32_CHUNK_QUADS, 2, 4><<<(unsigned)nslabs, 512, 0, st>>>(tab);
       if (last) k_trsm_mixed_last<64, 4, 2, 4, FP32_CHUNK_QUADS><<<(unsigned)nslabs, 512, 0, st>>>(tab);
       break;
     case 128:
-      k_trsm_mixed<128, 4, 2, 2, FP32_CHUNK_QUADS><<<(unsigned)nslabs, 512, 0, st>>>(tab);
+      k_trsm_mixed<128, 4, 2, 4, FP32_CHUNK_QUADS, 2, 4><<<(unsigned)nslabs, 512, 0, st>>>(tab);
       if (last) k_trsm_mixed_last<128, 4, 2, 2, FP32_CHUNK_QUADS><<<(unsigned)nslabs, 512, 0, st>>>(tab);
       break;
     default: return hipErrorInvalidValue;
