@@ -56,10 +56,10 @@ def parse():
     ap.add_argument("--block", type=int, default=None, help="SNPs per solve call (default 4096)")
     ap.add_argument("--streams", type=int, default=1)
     ap.add_argument("--batch", type=int, default=None,
-                    help="blocks whitened per launch (default: enough columns for one slab of the "
-                         "form's widest width per CU: 64 in FP64, 128 in FP32_REFINE)")
+                    help="blocks whitened per launch (default: enough columns for one slab of "
+                         "the widest width, 128, per CU)")
     ap.add_argument("--slab-cols", type=int, default=0,
-                    help="columns per work-group of the solve: 16, 32, 64 (128 in FP32_REFINE), "
+                    help="columns per work-group of the solve: 16 (FP64 only), 32, 64, 128, "
                          "or 0 to let the library choose per launch")
     ap.add_argument("--forms", default="fp64,fp32_refine",
                     help="precisions to time, the first is the headline")
@@ -588,7 +588,7 @@ def main():
         # blocks per launch: one slab of the widest width per CU
         if args.batch:
             return args.batch
-        widest = args.slab_cols or (128 if prec == "fp32_refine" else 64)
+        widest = args.slab_cols or 128
         return max(1, cus * widest // (block * w.p_R))
     batch = batch_for(forms[0])
 

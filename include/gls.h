@@ -158,17 +158,16 @@ int gls_whiten_block(gls_handle h, int64_t ncols, const int8_t* X, int64_t ldx,
 
 /* ---- tuning and measurement -------------------------------------------- */
 
-/* Columns of genotypes per work-group of the triangular-solve kernel:
- * 16, 32 or 64 in FP64, 32, 64 or 128 in FP32_REFINE (the other form's
- * extra width returns GLS_E_UNSUPPORTED, any other value -2), or 0 (the
+/* Columns of genotypes per work-group of the triangular-solve kernel: 16
+ * (FP64 only; GLS_E_UNSUPPORTED in FP32_REFINE), 32, 64 or 128, or 0 (the
  * default) to choose per launch: the narrowest width whose slabs still
- * number at most one per compute unit, else 64 — a slab's walk down the
+ * number at most one per compute unit, else 128 — a slab's walk down the
  * row blocks takes about the same time whatever runs beside it, so small
  * launches finish sooner in narrow slabs and full launches run best in wide
- * ones.  A performance knob only: every column is whitened by the same
- * sequence of operations whatever its slab, so results are bitwise
- * independent of it.  Items of one gls_solve_multi call must share the
- * setting. */
+ * ones.  Other values return -2.  A performance knob only: every column is
+ * whitened by the same sequence of operations whatever its slab, so results
+ * are bitwise independent of it.  Items of one gls_solve_multi call must
+ * share the setting. */
 int gls_set_slab_cols(gls_handle h, int cols);
 
 /* Kernel timing.  While enabled, every launch of the triangular-solve

@@ -225,12 +225,9 @@ struct TimedScope {
 // compute unit (measured at n = 10^4, FP64: 576 to 4,096 columns in 9.9 ms
 // with 16-column slabs against 22.9 ms with 64; 8,192 columns in 16.4 ms
 // with 32 against 23.3 ms), while launches that fill the chip are fastest
-// with the widest: 64 in FP64, 128 in FP32_REFINE (measured at n = 10^4:
-// 32,768 columns in 32.2 ms with 128-column slabs against 34.6 ms with 64).
-// The FP32_REFINE kernel has no 16-column form, the FP64 one no 128-column
-// form.  A width set on the handle overrides the choice.
-int widest_slab(const gls_handle h) { return h->c->prec == GLS_FP32_REFINE ? MAX_C : DEFAULT_C; }
-
+// with the widest, 128 (32,768 columns: FP64 49.6 ms against 52.6 ms with
+// 64, FP32_REFINE 32.2 ms against 34.6 ms).  The FP32_REFINE kernel has no
+// 16-column form.  A width set on the handle overrides the choice.
 int slab_cols_for(const gls_work* items, int64_t count) {
   const gls_handle h = items[0].h;
   if (h->C != 0) return h->C;
@@ -242,10 +239,9 @@ int slab_cols_for(const gls_work* items, int64_t count) {
     s64 += (ncols + 63) / 64;
   }
   const int64_t cus = h->c->cus;
-  const bool fp32 = h->c->prec == GLS_FP32_REFINE;
-  if (!fp32 && s16 <= cus) return 16;
+  if (h->c->prec != GLS_FP32_REFINE && s16 <= cus) return 16;
   if (s32 <= cus) return 32;
-  if (!fp32 || s64 <= cus) return 64;
+  if (s64 <= cus) return 64;
   return 128;
 }
 
@@ -466,7 +462,7 @@ int gls_solve_multi(const gls_work* items, int64_t count, void* stream) {
   if (count == 0) return GLS_OK;
   if (!items) return -1;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  const int C = items[0].h ? items[0].h->C : DEFAULT_C;
+  const int C = items[0].h ? items[0].h->C : 0;
   const int prec = items[0].h ? items[0].h->c->prec : GLS_FP64;
   for (int64_t i = 0; i < count; i++) {
     const gls_work& w = items[i];
@@ -578,7 +574,6 @@ int gls_set_slab_cols(gls_handle h, int cols) {
   if (!h) return -1;
   if (cols != 0 && cols != 16 && cols != 32 && cols != 64 && cols != 128) return -2;
   if (h->c->prec == GLS_FP32_REFINE && cols == 16) return GLS_E_UNSUPPORTED;
-  if (h->c->prec != GLS_FP32_REFINE && cols == 128) return GLS_E_UNSUPPORTED;
   h->C = cols;
   return GLS_OK;
 }
@@ -637,7 +632,7 @@ int gls_solve_stream(gls_handle h, int64_t snp_begin, int64_t snp_end, int64_t b
   // I/O happens per block of `block` problems; the device solves
   // superblocks of `group` consecutive blocks so that one launch has at
   // least one slab per CU (results do not depend on the grouping)
-  const int64_t target_cols = h->c->cus * (int64_t)(h->C ? h->C : widest_slab(h));
+  const int64_t target_cols = h->c->cus * (int64_t)(h->C ? h->C : MAX_C);
   const int64_t group = std::max<int64_t>(1, (target_cols + block * p_R - 1) / (block * p_R));
   const int64_t sbk = group * block;  // problems per superblock
   const int64_t cols = sbk * p_R;

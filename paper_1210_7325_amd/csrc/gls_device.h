@@ -65,6 +65,28 @@ __device__ __forceinline__ size_t slab_index(int64_t row, int64_t col, int C, in
 }
 
 
+// s_waitcnt vmcnt(N) lgkmcnt(0) (gfx9 encoding; expcnt left free)
+template <int N>
+__device__ __forceinline__ void wait_vm_lgkm0() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | ((N >> 4) << 14));
+}
+
+// Barrier without a memory fence (the caller has waited for what it needs);
+// the compiler may move no memory access across it.
+__device__ __forceinline__ void barrier_only() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+// One 1 KB chunk (64 lanes x 16 bytes) from global memory straight into LDS
+// at dst + 16 bytes * lane (global_load_lds_dwordx4; dst is wave-uniform).
+// Completion is counted by vmcnt.
+__device__ __forceinline__ void chunk_to_lds(const void* src, void* dst) {
+  __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
+}
+
 template <typename TIn>
 __device__ __forceinline__ double load_x(const TIn* __restrict__ X, int64_t ldx, int64_t row,
                                          int64_t col, int64_t n, int64_t ncols) {

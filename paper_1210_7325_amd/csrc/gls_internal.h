@@ -6,8 +6,7 @@
 namespace gls {
 
 constexpr int NB = 128;       // row block of the factorization and the solve
-constexpr int DEFAULT_C = 64; // widest slab of genotype columns of the FP64 solve (16, 32 or 64)
-constexpr int MAX_C = 128;    // widest of the FP32_REFINE solve (32, 64 or 128); workspaces come in multiples of it
+constexpr int MAX_C = 128;    // widest slab of genotype columns (16 - 128); workspaces come in multiples of it
 constexpr int MAXP = 20;      // p = p_L + p_R <= 20 (Sec. 1)
 constexpr int MAXT = 8;       // phenotypes per call
 constexpr int MAX_INLINE_JOBS = 16;

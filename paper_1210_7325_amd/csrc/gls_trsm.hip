@@ -21,7 +21,87 @@ __host__ __device__ inline bool last_block_split(int64_t n, int K, int RW) {
   return K > 1 && n - (int64_t)(K - 1) * NB <= RW;
 }
 
-template <int C, int WR, int WC, int D, typename TIn>
+template <int C, int G>
+constexpr int staged_ring_doubles(int S) { return S * G * (NB / 16 + C / 16) * 128; }
+
+// The off-diagonal sum acc = sum_{j<k} L_kj W_j for one row block with the
+// operands staged through LDS: a stage is G k-step pairs, i.e. G (NB/16 +
+// C/16) chunks of 1 KB (the strip tiles of all NB rows and the W tiles of
+// all C columns), copied by the work-group's waves straight into one of S
+// LDS slots, S - 1 stages ahead.  Every wave then reads its own tiles from
+// LDS: each operand byte crosses the L1 cache once per work-group, and the
+// stages in flight cost no registers.  A wave waits for its own copies of a
+// stage (vmcnt), then the barrier makes all of them visible and frees the
+// slot read in the previous stage, which the next copy then fills.  The
+// products are the same MFMAs in the same order as the register ring's.
+template <int C, int WR, int WC, int G, int S>
+__device__ __forceinline__ void gemm_staged_f64(const double* __restrict__ Lk,
+                                                const double* __restrict__ Wslab, int npairs,
+                                                double* __restrict__ ring_base,
+                                                d4 (&acc)[NB / WR / 16][C / WC / 16]) {
+  constexpr int RT = NB / WR / 16, CT = C / WC / 16, CTS = C / 16, NT = NB / 16;
+  constexpr int NW = WR * WC;
+  constexpr int CL = G * NT;           // chunks of L per stage
+  constexpr int CPS = G * (NT + CTS);  // chunks per stage
+  constexpr int LPW_HI = (CPS + NW - 1) / NW, LPW_LO = CPS / NW;
+  double(*ring)[CPS * 128] = reinterpret_cast<double(*)[CPS * 128]>(ring_base);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x % 64;
+  const int wr = wave / WC, wc = wave % WC;
+  const int nst = npairs / G;
+  // this wave's copies of stage st into slot sl (chunk c = wave + i NW)
+  auto issue = [&](int st, int sl) {
+#pragma unroll
+    for (int i = 0; i < LPW_HI; i++) {
+      const int c = wave + i * NW;
+      if (c < CPS) {
+        const double* src = c < CL ? Lk + ((size_t)st * CL + c) * 128 + lane * 2
+                                   : Wslab + ((size_t)st * G * CTS + (c - CL)) * 128 + lane * 2;
+        chunk_to_lds(src, &ring[sl][c * 128]);
+      }
+    }
+  };
+#pragma unroll
+  for (int sl = 0; sl < S - 1; sl++) issue(sl < nst ? sl : nst - 1, sl);
+  for (int st = 0; st < nst; st++) {
+    // stage st is in LDS for every wave; every wave is done with slot (st-1)%S
+    if (LPW_HI == LPW_LO || wave < CPS % NW)
+      wait_vm_lgkm0<(S - 2) * LPW_HI>();
+    else
+      wait_vm_lgkm0<(S - 2) * LPW_LO>();
+    barrier_only();
+    {
+      // refill the freed slot with stage st + S - 1 (clamped: the tail
+      // copies are never read)
+      const int nx = st + S - 1;
+      issue(nx < nst ? nx : nst - 1, nx % S);
+    }
+    const double* __restrict__ slot = ring[st % S];
+#pragma unroll
+    for (int g = 0; g < G; g++) {
+      d2 a[RT], b[CT];
+#pragma unroll
+      for (int rt = 0; rt < RT; rt++)
+        a[rt] = *reinterpret_cast<const d2*>(slot + (g * NT + wr * RT + rt) * 128 + lane * 2);
+#pragma unroll
+      for (int ct = 0; ct < CT; ct++)
+        b[ct] = *reinterpret_cast<const d2*>(slot + (CL + g * CTS + wc * CT + ct) * 128 + lane * 2);
+#pragma unroll
+      for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+        for (int ct = 0; ct < CT; ct++) {
+          acc[rt][ct] = MFMA64(a[rt].x, b[ct].x, acc[rt][ct]);
+          acc[rt][ct] = MFMA64(a[rt].y, b[ct].y, acc[rt][ct]);
+        }
+    }
+    asm volatile("" ::: "memory");
+  }
+  // the ring shares its LDS with the right-hand side staged next: the tail
+  // copies land and every wave is done reading before that is written
+  wait_vm_lgkm0<0>();
+  barrier_only();
+}
+
+template <int C, int WR, int WC, int D, typename TIn, int G = 1, int S = 0>
 __global__ __launch_bounds__(64 * WR * WC) void k_trsm(const JobTable tab) {
   constexpr int RW = NB / WR, RT = RW / 16;
   constexpr int CW = C / WC, CT = CW / 16;
@@ -29,7 +109,11 @@ __global__ __launch_bounds__(64 * WR * WC) void k_trsm(const JobTable tab) {
   constexpr int NPB = NB / 8;  // k-step pairs per row block
   static_assert(RT >= 1 && CT >= 1, "tile shape");
   static_assert(NPB % D == 0, "prefetch depth must divide the pairs of a block");
-  __shared__ __attribute__((aligned(16))) double Rl[NB * C];
+  static_assert(S == 0 || (NPB % G == 0 && S >= 2), "staging");
+  // R_k for the diagonal step; with staged operands (S > 0) the same LDS
+  // holds the stage ring during the GEMM
+  constexpr int RL_DOUBLES = NB * C > staged_ring_doubles<C, G>(S) ? NB * C : staged_ring_doubles<C, G>(S);
+  __shared__ __attribute__((aligned(16))) double Rl[RL_DOUBLES];
 
   // find the job of this slab
   int jb = 0;
@@ -92,7 +176,9 @@ __global__ __launch_bounds__(64 * WR * WC) void k_trsm(const JobTable tab) {
     const double* __restrict__ Ls = Lstrips + strip_offset(k) + (size_t)(wr * RT) * 128 + lane * 2;
     const double* __restrict__ Wb = Wslab + (size_t)(wc * CT) * 128 + lane * 2;
     const int npairs = k * NPB;
-    if (npairs > 0) {
+    if constexpr (S > 0) {
+      if (npairs > 0) gemm_staged_f64<C, WR, WC, G, S>(Lstrips + strip_offset(k), Wslab, npairs, Rl, acc);
+    } else if (npairs > 0) {
       d2 a[D][RT], b[D][CT];
 #pragma unroll
       for (int s = 0; s < D; s++) {
@@ -357,6 +443,12 @@ hipError_t launch_trsm_i8(const JobTable& tab, int64_t nslabs, int C, hipStream_
     case 64:
       k_trsm<64, 4, 2, TRSM_DEPTH, int8_t><<<(unsigned)nslabs, 512, 0, st>>>(tab);
       if (last) k_trsm_last<64, 4, 2, TRSM_DEPTH><<<(unsigned)nslabs, 512, 0, st>>>(tab);
+      break;
+    case 128:
+      // staged operands: a 32 x 64 tile per wave fits in registers only
+      // without the register ring
+      k_trsm<128, 4, 2, TRSM_DEPTH, int8_t, 2, 4><<<(unsigned)nslabs, 512, 0, st>>>(tab);
+      if (last) k_trsm_last<128, 4, 2, 2><<<(unsigned)nslabs, 512, 0, st>>>(tab);
       break;
     default: return hipErrorInvalidValue;
   }

@@ -10,20 +10,6 @@ __host__ __device__ inline bool mixed_last_block_split(int64_t n, int K, int RW)
   return K > 1 && n - (int64_t)(K - 1) * NB <= RW;
 }
 
-// vmcnt <= N with lgkmcnt = 0 (gfx9 s_waitcnt encoding; expcnt left free)
-template <int N>
-__device__ __forceinline__ void wait_vm_lgkm0() {
-  static_assert(N >= 0 && N < 64, "vmcnt range");
-  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | ((N >> 4) << 14));
-}
-
-// One 1 KB chunk (64 lanes x 16 bytes) from global memory straight into LDS
-// at dst + 16 * lane (global_load_lds_dwordx4; dst is wave-uniform).
-__device__ __forceinline__ void chunk_to_lds(const float* src, float* dst) {
-  __builtin_amdgcn_global_load_lds((const void*)src, (__attribute__((address_space(3))) void*)dst, 16,
-                                   0, 0);
-}
-
 // The off-diagonal sum acc = sum_{j<k} L_kj W_j of the mixed solve for one
 // row block, with the operands staged through LDS: a stage is G k-step quads,
 // i.e. G (NB/16 + C/16) chunks of 1 KB (the L32 strip tiles of all NB rows
@@ -76,9 +62,7 @@ __device__ __forceinline__ void gemm_staged(const float* __restrict__ Lk, const 
       wait_vm_lgkm0<(S - 2) * LPW_HI>();
     else
       wait_vm_lgkm0<(S - 2) * LPW_LO>();
-    asm volatile("" ::: "memory");
-    __builtin_amdgcn_s_barrier();
-    asm volatile("" ::: "memory");
+    barrier_only();
     {
       // refill the freed slot with stage st + S - 1 (clamped: the tail
       // copies are never read)
@@ -118,9 +102,7 @@ __device__ __forceinline__ void gemm_staged(const float* __restrict__ Lk, const 
   // the ring shares its LDS with the right-hand side staged next: the tail
   // copies land and every wave is done reading before that is written
   wait_vm_lgkm0<0>();
-  asm volatile("" ::: "memory");
-  __builtin_amdgcn_s_barrier();
-  asm volatile("" ::: "memory");
+  barrier_only();
 }
 
 // Mixed-precision blocked lower solve W = L^{-1}(X - 1 s^T): as k_trsm, but

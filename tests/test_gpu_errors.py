@@ -56,10 +56,10 @@ def test_out_of_order_and_invalid_calls(G, problem):
     assert G.gls_solve_block(h, w.m, 1, XR.data_ptr(), w.n, B.data_ptr(), w.p - 1, None) < 0
     assert G.gls_solve_block(h, w.m, 1, XR.data_ptr(), w.n, None, w.p, None) < 0
     assert G.gls_solve_block(h, 0, 1, None, w.n, None, w.p, None) == 0      # empty block
-    # slab widths: 16/32/64 (and 128 in the FP32_REFINE form) only
+    # slab widths: 16/32/64/128 only
     assert G.gls_set_slab_cols(h, 48) == -2
     assert G.gls_set_slab_cols(h, 256) == -2
-    assert G.gls_set_slab_cols(h, 128) == G.GLS_E_UNSUPPORTED
+    assert G.gls_set_slab_cols(h, 128) == 0 and G.gls_set_slab_cols(h, 0) == 0
     # an impossible workspace fails cleanly and leaves the handle usable
     assert G.gls_reserve(h, 1 << 40) == G.GLS_E_OOM
     assert G.gls_solve_block(h, w.m, 1, XR.data_ptr(), w.n, B.data_ptr(), w.p, info.data_ptr()) == 0

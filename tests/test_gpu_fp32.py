@@ -146,8 +146,9 @@ def test_fp32_refine_deterministic_and_multi(G):
 
 def test_fp32_refine_full_n_sampled(G):
     """n = 10,000, p = 20 (p_L = 16, p_R = 4), maf ~ U[0.01, 0.5]: four blocks
-    of 4096 problems (16,384 genotype columns per block) in one launch as the
-    benchmark runs them; 200 sampled problems checked against the oracle."""
+    of 4096 problems (16,384 genotype columns per block), two per launch in
+    128-column slabs as the benchmark runs this form; 200 sampled problems
+    checked against the oracle."""
     import bench
     w = dg.MIXED
     m = 4 * w.block
@@ -159,7 +160,7 @@ def test_fp32_refine_full_n_sampled(G):
     info = torch.full((m,), -7, dtype=torch.int32, device="cuda")
     stream = torch.cuda.Stream()
     bench.run_step(G, torch, torch.from_numpy(M).cuda(), to_dev(XL), to_dev(Y), dXR, w, m,
-                   w.block, [stream], 64, Bout, info, batch=4, precision="fp32_refine")
+                   w.block, [stream], 0, Bout, info, batch=2, precision="fp32_refine")
     torch.cuda.synchronize()
     assert int((info != 0).sum()) == 0
     idx = np.unique(np.concatenate([[0, 1, m - 1], np.random.default_rng(2).choice(m, 197, replace=False)]))

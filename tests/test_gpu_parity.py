@@ -171,13 +171,13 @@ def test_deterministic_and_block_independent(G):
 def test_slab_width_choice_is_bitwise_neutral(G, prec):
     """Automatic per-launch slab width (the default) against every fixed
     width: the same bits, for launches small enough to pick 16 or 32 and
-    large enough to pick 64 columns per work-group."""
+    large enough to pick 128 columns per work-group."""
     say("slab widths", prec)
     from paper_1210_7325_amd import gls
     w, M, XL, Y, XR = small_problem(700, m=20000)
     c = gls.Cohort(to_dev(M), precision=prec).whiten_fixed(to_dev(XL), to_dev(Y), intercept_col=0)
     dXR = to_dev(XR)
-    widths = (32, 64, 128) if prec == "fp32_refine" else (16, 32, 64)
+    widths = (32, 64, 128) if prec == "fp32_refine" else (16, 32, 64, 128)
     for m in (100, 5000, 20000):
         c.set_slab_cols(0)
         ref, _ = c.solve_block(dXR[:, :m])
@@ -187,6 +187,32 @@ def test_slab_width_choice_is_bitwise_neutral(G, prec):
             B, _ = c.solve_block(dXR[:, :m])
             assert np.array_equal(B.cpu().numpy(), ref), (m, C)
     c.free()
+
+
+@pytest.mark.parametrize("n,m,block", [(660, 300, 300), (1000, 700, 333)])
+def test_wide_slabs_parity(G, n, m, block):
+    """128 genotype columns per work-group (operands staged through LDS):
+    within the bound of the oracle and the same bits as 64.  n = 660 leaves
+    its last row block of 20 rows to the last-block kernel; n = 1000 ends in
+    a partial row block of the main kernel; both blocks end in a partial
+    slab."""
+    say("128-column slabs", n, m, block)
+    from paper_1210_7325_amd import gls
+    w, M, XL, Y, XR = small_problem(n, m=m, seed=n + 3)
+    c = gls.Cohort(to_dev(M)).whiten_fixed(to_dev(XL), to_dev(Y))
+    dXR = to_dev(XR)
+    outs = {}
+    for C in (128, 64):
+        c.set_slab_cols(C)
+        parts = [c.solve_block(dXR[:, a:min(m, a + block)]) for a in range(0, m, block)]
+        assert all(np.all(i.cpu().numpy() == 0) for _, i in parts)
+        outs[C] = torch.cat([b for b, _ in parts]).cpu().numpy()
+    c.free()
+    ref = orc.gls_sequence(M, XL, XR, Y, 1)
+    err = orc.relative_error(outs[128], ref)
+    say("max rel err", err.max())
+    assert err.max() < TOL_B
+    assert np.array_equal(outs[128], outs[64])
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32_refine"])
@@ -258,10 +284,10 @@ def test_forked_streams_equal(G):
 
 
 def test_full_scale_sampled_in_bench_configuration(G):
-    """n = 10,000, p = 4, m = 1,000,000 in blocks of 4096, four blocks per
-    launch exactly as bench.py times it; 300 problems sampled across the
-    whole sequence (first, last partial block, and a stride) checked one by
-    one against the oracle."""
+    """n = 10,000, p = 4, m = 1,000,000 in blocks of 4096, eight blocks per
+    launch in slabs of the automatic width (128 columns) exactly as bench.py
+    times it; 300 problems sampled across the whole sequence (first, last
+    partial block, and a stride) checked one by one against the oracle."""
     import bench
     w = dg.SCALE
     say("full scale", w.name)
@@ -273,7 +299,7 @@ def test_full_scale_sampled_in_bench_configuration(G):
     Bout = torch.empty((w.m, w.t, w.p), dtype=torch.float64, device="cuda")
     info = torch.full((w.m,), -7, dtype=torch.int32, device="cuda")
     stream = torch.cuda.Stream()
-    bench.run_step(G, torch, dM, dXL, dY, dXR, w, w.m, w.block, [stream], 64, Bout, info, batch=4)
+    bench.run_step(G, torch, dM, dXL, dY, dXR, w, w.m, w.block, [stream], 0, Bout, info, batch=8)
     torch.cuda.synchronize()
     assert int((info != 0).sum()) == 0
     rng = np.random.default_rng(5)
