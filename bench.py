@@ -96,7 +96,7 @@ def measured_traffic(batch, slab_cols, precision):
         kv = dict(l.split(": ", 1) for l in open(path).read().splitlines() if ": " in l)
         if kv.get("kernel_source_sha256") != trsm_source_digest() \
                 or int(kv["blocks_per_launch"]) != batch \
-                or slab_cols not in (0, 64):
+                or slab_cols not in (0, int(kv["slab_cols"])):
             return None
         return float(kv["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
@@ -439,9 +439,9 @@ def stream_bench(args):
 def ablation_bench(args):
     """The grouping ablation of the paper's Fig. 2 on the GPU (n = 10^4, p = 4):
     the same whitening and per-problem solves with the genotype columns
-    grouped into launches of 64 .. 16,384 right-hand sides, with 64-column
-    slabs (1 .. 256 of them for 256 compute units) and with the library's
-    per-launch choice of slab width.  The paper groups many trsv into one
+    grouped into launches of 64 .. 32,768 right-hand sides, with 64-column
+    slabs (1 .. 512 of them for 256 compute units) and with the library's
+    per-launch choice of slab width (16 .. 128 columns).  The paper groups many trsv into one
     trsm for BLAS-3 efficiency on a CPU; on the GPU the grouping is what
     fills the chip, and a launch of one slab leaves 255 compute units idle.
     Each setting times four launches after a warm-up; the rate is problems
@@ -460,7 +460,7 @@ def ablation_bench(args):
     dXR = upload_genotypes(torch, w, mmax)
     B = torch.empty((mmax, w.t, w.p), dtype=torch.float64, device="cuda")
     info = torch.empty((mmax,), dtype=torch.int32, device="cuda")
-    for slab, cols in [(sc, cl) for sc in (64, 0) for cl in (64, 256, 1024, 4096, 16384)]:
+    for slab, cols in [(sc, cl) for sc in (64, 0) for cl in (64, 256, 1024, 4096, 16384, 32768)]:
         c.set_slab_cols(slab)
         batch = max(1, cols // 4096)
         block = cols // batch

@@ -219,29 +219,37 @@ struct TimedScope {
   ~TimedScope() { end(); }
 };
 
-// Slab width of one launch.  A slab's walk down the row blocks takes about
-// the same time whatever else runs, so a launch of few columns is fastest
-// with the narrowest slabs that still give at most one work-group per
-// compute unit (measured at n = 10^4, FP64: 576 to 4,096 columns in 9.9 ms
-// with 16-column slabs against 22.9 ms with 64; 8,192 columns in 16.4 ms
-// with 32 against 23.3 ms), while launches that fill the chip are fastest
-// with the widest, 128 (32,768 columns: FP64 49.6 ms against 52.6 ms with
-// 64, FP32_REFINE 32.2 ms against 34.6 ms).  The FP32_REFINE kernel has no
-// 16-column form.  A width set on the handle overrides the choice.
+// Slab width of one launch.  A slab's walk down the row blocks takes a time
+// that grows with its width and with K^2 (K row blocks of its cohort), so a
+// launch of few columns is fastest with the narrowest slabs that still give
+// at most one work-group per compute unit (measured at n = 10^4, FP64: 576
+// to 4,096 columns in 9.9 ms with 16-column slabs against 22.9 ms with 64;
+// 8,192 columns in 16.4 ms with 32 against 23.3 ms).  Past 64 columns per
+// CU, 128-column slabs are about 6% faster per column (32,768 columns: FP64
+// 50.0 ms against 52.6 ms with 64, FP32_REFINE 32.2 ms against 34.6 ms), but
+// a 128-column slab takes twice as long as a 64-column one: they are chosen
+// only when the 64-column slabs of the launch, spread over the CUs, would
+// take at least two of its longest slab, so that no slab of a large cohort
+// becomes the critical path of a launch that mixes cohorts.  The
+// FP32_REFINE kernel has no 16-column form.  A width set on the handle
+// overrides the choice.
 int slab_cols_for(const gls_work* items, int64_t count) {
   const gls_handle h = items[0].h;
   if (h->C != 0) return h->C;
-  int64_t s16 = 0, s32 = 0, s64 = 0;
+  int64_t s16 = 0, s32 = 0, s64 = 0, work64 = 0, kmax2 = 0;
   for (int64_t i = 0; i < count; i++) {
     const int64_t ncols = items[i].nsnp * items[i].p_R;
+    const int64_t k2 = (int64_t)items[i].h->c->K * items[i].h->c->K;
     s16 += (ncols + 15) / 16;
     s32 += (ncols + 31) / 32;
     s64 += (ncols + 63) / 64;
+    work64 += (ncols + 63) / 64 * k2;
+    if (ncols > 0) kmax2 = std::max(kmax2, k2);
   }
   const int64_t cus = h->c->cus;
   if (h->c->prec != GLS_FP32_REFINE && s16 <= cus) return 16;
   if (s32 <= cus) return 32;
-  if (s64 <= cus) return 64;
+  if (s64 <= cus || work64 < 2 * cus * kmax2) return 64;
   return 128;
 }
 
