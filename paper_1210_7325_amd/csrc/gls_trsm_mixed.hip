@@ -51,11 +51,6 @@ __device__ __forceinline__ void gemm_staged(const float* __restrict__ Lk, const 
   };
 #pragma unroll
   for (int sl = 0; sl < S - 1; sl++) issue(sl < nst ? sl : nst - 1, sl);
-  f4 c32[RT][CT];
-#pragma unroll
-  for (int a = 0; a < RT; a++)
-#pragma unroll
-    for (int b = 0; b < CT; b++) c32[a][b] = (f4){0, 0, 0, 0};
   for (int st = 0; st < nst; st++) {
     // stage st is in LDS for every wave; every wave is done with slot (st-1)%S
     if (LPW_HI == LPW_LO || wave < CPS % NW)
@@ -79,22 +74,19 @@ __device__ __forceinline__ void gemm_staged(const float* __restrict__ Lk, const 
 #pragma unroll
       for (int ct = 0; ct < CT; ct++)
         b[ct] = *reinterpret_cast<const f4*>(slot + (CL + g * CTS + wc * CT + ct) * 256 + lane * 4);
+      // each tile's quad is a fresh FP32 chain (started from zero) folded
+      // into the FP64 sum as soon as it is done: the fold of one tile has
+      // no dependence on the next tile's MFMAs, so the two overlap
 #pragma unroll
       for (int rt = 0; rt < RT; rt++)
 #pragma unroll
         for (int ct = 0; ct < CT; ct++) {
-          c32[rt][ct] = MFMA32(a[rt].x, b[ct].x, c32[rt][ct]);
-          c32[rt][ct] = MFMA32(a[rt].y, b[ct].y, c32[rt][ct]);
-          c32[rt][ct] = MFMA32(a[rt].z, b[ct].z, c32[rt][ct]);
-          c32[rt][ct] = MFMA32(a[rt].w, b[ct].w, c32[rt][ct]);
-        }
+          f4 c = MFMA32(a[rt].x, b[ct].x, ((f4){0, 0, 0, 0}));
+          c = MFMA32(a[rt].y, b[ct].y, c);
+          c = MFMA32(a[rt].z, b[ct].z, c);
+          c = MFMA32(a[rt].w, b[ct].w, c);
 #pragma unroll
-      for (int rt = 0; rt < RT; rt++)
-#pragma unroll
-        for (int ct = 0; ct < CT; ct++) {
-#pragma unroll
-          for (int i = 0; i < 4; i++) acc[rt][ct][i] += (double)c32[rt][ct][i];
-          c32[rt][ct] = (f4){0, 0, 0, 0};
+          for (int i = 0; i < 4; i++) acc[rt][ct][i] += (double)c[i];
         }
     }
     asm volatile("" ::: "memory");

@@ -73,12 +73,14 @@ def test_fp32_refine_parity(G, n, pL, pR, t, m, block):
     assert err.max() < TOL_FP32_FORM
 
 
-@pytest.mark.parametrize("n,m,block", [(660, 300, 300), (1000, 700, 333)])
+@pytest.mark.parametrize("n,m,block", [(660, 300, 300), (1000, 700, 333), (129, 90, 45),
+                                       (200, 300, 300)])
 def test_fp32_refine_wide_slabs(G, n, m, block):
-    """128 genotype columns per work-group (the FP32_REFINE form only): within
-    the bound of the oracle and the same bits as 64.  n = 660 leaves its last
-    row block of 20 rows to the last-block kernel; n = 1000 ends in a partial
-    row block of the main kernel; both blocks end in a partial slab."""
+    """128 genotype columns per work-group: within the bound of the oracle
+    and the same bits as 64.  n = 660 leaves its last row block of 20 rows
+    to the last-block kernel; n = 1000 ends in a partial row block of the
+    main kernel; n = 129 and n = 200 have two row blocks; every block ends
+    in a partial slab."""
     say("fp32 form, 128-column slabs", n, m, block)
     w, M, XL, Y, XR = problem(n, 3, 1, m, seed=n + 1)
     B, info = run(G, M, XL, Y, XR, 1, block, slab=128)

@@ -189,13 +189,16 @@ def test_slab_width_choice_is_bitwise_neutral(G, prec):
     c.free()
 
 
-@pytest.mark.parametrize("n,m,block", [(660, 300, 300), (1000, 700, 333)])
+@pytest.mark.parametrize("n,m,block", [(660, 300, 300), (1000, 700, 333), (64, 50, 50),
+                                       (129, 90, 45), (200, 300, 300)])
 def test_wide_slabs_parity(G, n, m, block):
     """128 genotype columns per work-group (operands staged through LDS):
     within the bound of the oracle and the same bits as 64.  n = 660 leaves
     its last row block of 20 rows to the last-block kernel; n = 1000 ends in
-    a partial row block of the main kernel; both blocks end in a partial
-    slab."""
+    a partial row block of the main kernel; n = 64 has one row block (no
+    off-diagonal product), n = 129 two with the second left to the
+    last-block kernel, n = 200 two with one stage ring pass; every block
+    ends in a partial slab."""
     say("128-column slabs", n, m, block)
     from paper_1210_7325_amd import gls
     w, M, XL, Y, XR = small_problem(n, m=m, seed=n + 3)
