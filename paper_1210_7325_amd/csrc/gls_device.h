@@ -72,6 +72,9 @@ __device__ __forceinline__ void wait_vm_lgkm0() {
   __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | ((N >> 4) << 14));
 }
 
+// s_waitcnt lgkmcnt(0) alone (vmcnt and expcnt left free)
+__device__ __forceinline__ void wait_lgkm0() { __builtin_amdgcn_s_waitcnt(15 | (7 << 4) | (3 << 14)); }
+
 // Barrier without a memory fence (the caller has waited for what it needs);
 // the compiler may move no memory access across it.
 __device__ __forceinline__ void barrier_only() {

@@ -25,20 +25,27 @@ template <int C, int G>
 constexpr int staged_ring_doubles(int S) { return S * G * (NB / 16 + C / 16) * 128; }
 
 // The off-diagonal sum acc = sum_{j<k} L_kj W_j for one row block with the
-// operands staged through LDS: a stage is G k-step pairs, i.e. G (NB/16 +
+// operands staged through LDS: a stage is two k-step pairs, i.e. 2 (NB/16 +
 // C/16) chunks of 1 KB (the strip tiles of all NB rows and the W tiles of
 // all C columns), copied by the work-group's waves straight into one of S
 // LDS slots, S - 1 stages ahead.  Every wave then reads its own tiles from
 // LDS: each operand byte crosses the L1 cache once per work-group, and the
-// stages in flight cost no registers.  A wave waits for its own copies of a
-// stage (vmcnt), then the barrier makes all of them visible and frees the
-// slot read in the previous stage, which the next copy then fills.  The
-// products are the same MFMAs in the same order as the register ring's.
+// stages in flight cost no registers.
+//
+// The barrier sits in the middle of a stage, so that MFMAs are always ready
+// on both sides of it: a wave reads the second pair of stage st, runs the
+// first pair's MFMAs, waits for its own copies of stage st+1 (vmcnt) and
+// for its LDS reads, and passes the barrier, which makes stage st+1 visible
+// to everyone and certifies that every wave has read all of stage st; it
+// then refills stage st's slot with stage st+S, reads the first pair of
+// stage st+1 and runs the second pair of stage st while those reads land.
+// The products are the same MFMAs in the same order as the register ring's.
 template <int C, int WR, int WC, int G, int S>
 __device__ __forceinline__ void gemm_staged_f64(const double* __restrict__ Lk,
                                                 const double* __restrict__ Wslab, int npairs,
                                                 double* __restrict__ ring_base,
                                                 d4 (&acc)[NB / WR / 16][C / WC / 16]) {
+  static_assert(G == 2 && S >= 2, "two pairs per stage, split by the barrier");
   constexpr int RT = NB / WR / 16, CT = C / WC / 16, CTS = C / 16, NT = NB / 16;
   constexpr int NW = WR * WC;
   constexpr int CL = G * NT;           // chunks of L per stage
@@ -48,8 +55,12 @@ __device__ __forceinline__ void gemm_staged_f64(const double* __restrict__ Lk,
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x % 64;
   const int wr = wave / WC, wc = wave % WC;
   const int nst = npairs / G;
-  // this wave's copies of stage st into slot sl (chunk c = wave + i NW)
-  auto issue = [&](int st, int sl) {
+  const bool hi = LPW_HI == LPW_LO || wave < CPS % NW;  // this wave copies LPW_HI chunks
+  // this wave's copies of stage st (clamped to the last: the tail copies
+  // are never read) into its slot st % S (chunk c = wave + i NW)
+  auto issue = [&](int st) {
+    const int sl = st % S;
+    st = st < nst ? st : nst - 1;
 #pragma unroll
     for (int i = 0; i < LPW_HI; i++) {
       const int c = wave + i * NW;
@@ -60,39 +71,54 @@ __device__ __forceinline__ void gemm_staged_f64(const double* __restrict__ Lk,
       }
     }
   };
+  auto read_pair = [&](int st, int g, d2 (&a)[RT], d2 (&b)[CT]) {
+    const double* __restrict__ slot = ring[st % S];
 #pragma unroll
-  for (int sl = 0; sl < S - 1; sl++) issue(sl < nst ? sl : nst - 1, sl);
+    for (int rt = 0; rt < RT; rt++)
+      a[rt] = *reinterpret_cast<const d2*>(slot + (g * NT + wr * RT + rt) * 128 + lane * 2);
+#pragma unroll
+    for (int ct = 0; ct < CT; ct++)
+      b[ct] = *reinterpret_cast<const d2*>(slot + (CL + g * CTS + wc * CT + ct) * 128 + lane * 2);
+  };
+  auto mfma_pair = [&](const d2 (&a)[RT], const d2 (&b)[CT]) {
+#pragma unroll
+    for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+      for (int ct = 0; ct < CT; ct++) {
+        acc[rt][ct] = MFMA64(a[rt].x, b[ct].x, acc[rt][ct]);
+        acc[rt][ct] = MFMA64(a[rt].y, b[ct].y, acc[rt][ct]);
+      }
+  };
+  // all S slots filled, stage 0 visible
+#pragma unroll
+  for (int st = 0; st < S; st++) issue(st);
+  if (hi)
+    wait_vm_lgkm0<(S - 1) * LPW_HI>();
+  else
+    wait_vm_lgkm0<(S - 1) * LPW_LO>();
+  barrier_only();
+  d2 a0[RT], b0[CT], a1[RT], b1[CT];
+  read_pair(0, 0, a0, b0);
   for (int st = 0; st < nst; st++) {
-    // stage st is in LDS for every wave; every wave is done with slot (st-1)%S
-    if (LPW_HI == LPW_LO || wave < CPS % NW)
+    // the first pair's reads, issued a pair of MFMAs ago, have landed; waiting
+    // here keeps the wait for them from also covering the reads issued next
+    wait_lgkm0();
+    read_pair(st, 1, a1, b1);
+    // the reads go out before the MFMAs that hide them (the scheduler would
+    // otherwise sink them next to their use)
+    __builtin_amdgcn_sched_barrier(0);
+    mfma_pair(a0, b0);
+    __builtin_amdgcn_sched_barrier(0);
+    // stage st+1 is in LDS for every wave; every wave has read all of stage st
+    if (hi)
       wait_vm_lgkm0<(S - 2) * LPW_HI>();
     else
       wait_vm_lgkm0<(S - 2) * LPW_LO>();
     barrier_only();
-    {
-      // refill the freed slot with stage st + S - 1 (clamped: the tail
-      // copies are never read)
-      const int nx = st + S - 1;
-      issue(nx < nst ? nx : nst - 1, nx % S);
-    }
-    const double* __restrict__ slot = ring[st % S];
-#pragma unroll
-    for (int g = 0; g < G; g++) {
-      d2 a[RT], b[CT];
-#pragma unroll
-      for (int rt = 0; rt < RT; rt++)
-        a[rt] = *reinterpret_cast<const d2*>(slot + (g * NT + wr * RT + rt) * 128 + lane * 2);
-#pragma unroll
-      for (int ct = 0; ct < CT; ct++)
-        b[ct] = *reinterpret_cast<const d2*>(slot + (CL + g * CTS + wc * CT + ct) * 128 + lane * 2);
-#pragma unroll
-      for (int rt = 0; rt < RT; rt++)
-#pragma unroll
-        for (int ct = 0; ct < CT; ct++) {
-          acc[rt][ct] = MFMA64(a[rt].x, b[ct].x, acc[rt][ct]);
-          acc[rt][ct] = MFMA64(a[rt].y, b[ct].y, acc[rt][ct]);
-        }
-    }
+    issue(st + S);
+    read_pair(st + 1, 0, a0, b0);  // (past the last stage: a clamped copy, unused)
+    __builtin_amdgcn_sched_barrier(0);
+    mfma_pair(a1, b1);
     asm volatile("" ::: "memory");
   }
   // the ring shares its LDS with the right-hand side staged next: the tail

@@ -11,16 +11,19 @@ __host__ __device__ inline bool mixed_last_block_split(int64_t n, int K, int RW)
 }
 
 // The off-diagonal sum acc = sum_{j<k} L_kj W_j of the mixed solve for one
-// row block, with the operands staged through LDS: a stage is G k-step quads,
-// i.e. G (NB/16 + C/16) chunks of 1 KB (the L32 strip tiles of all NB rows
-// and the W32 tiles of all C columns), copied by the work-group's waves
-// straight into one of S LDS slots, S - 1 stages ahead.  Every wave then
-// reads its own tiles from LDS: each operand byte crosses the L1 cache once
-// per work-group, and the stages in flight cost no registers.  A wave waits
-// for its own copies of a stage (vmcnt), then the barrier makes all of them
-// visible and frees the slot read in the previous stage, which the next
-// copy then fills.  FP32 accumulation over one quad, then the FP64 running
-// sum, as in the register-ring form.
+// row block, with the operands staged through LDS: a stage is two k-step
+// quads, i.e. 2 (NB/16 + C/16) chunks of 1 KB (the L32 strip tiles of all
+// NB rows and the W32 tiles of all C columns), copied by the work-group's
+// waves straight into one of S LDS slots, S - 1 stages ahead.  Every wave
+// then reads its own tiles from LDS: each operand byte crosses the L1 cache
+// once per work-group, and the stages in flight cost no registers.  As in
+// the FP64 solve, the barrier sits in the middle of a stage: a wave reads
+// the second quad of stage st, runs the first quad, waits for its own
+// copies of stage st+1 and for its LDS reads, passes the barrier (stage st+1
+// visible to all, stage st read by all), refills stage st's slot with stage
+// st+S, reads the first quad of stage st+1 and runs the second quad of
+// stage st.  FP32 accumulation over one quad, then the FP64 running sum, as
+// in the register-ring form.
 template <int C, int G>
 constexpr int staged_ring_floats(int S) { return S * G * (NB / 16 + C / 16) * 256; }
 
@@ -28,6 +31,7 @@ template <int C, int WR, int WC, int G, int S>
 __device__ __forceinline__ void gemm_staged(const float* __restrict__ Lk, const float* __restrict__ W32slab,
                                             int nq, float* __restrict__ ring_base,
                                             d4 (&acc)[NB / WR / 16][C / WC / 16]) {
+  static_assert(G == 2 && S >= 2, "two quads per stage, split by the barrier");
   constexpr int RT = NB / WR / 16, CT = C / WC / 16, CTS = C / 16, NQB = NB / 16;
   constexpr int NW = WR * WC;
   constexpr int CL = G * NQB;          // chunks of L per stage
@@ -37,8 +41,12 @@ __device__ __forceinline__ void gemm_staged(const float* __restrict__ Lk, const 
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x % 64;
   const int wr = wave / WC, wc = wave % WC;
   const int nst = nq / G;
-  // this wave's copies of stage st into slot sl (chunk c = wave + i NW)
-  auto issue = [&](int st, int sl) {
+  const bool hi = LPW_HI == LPW_LO || wave < CPS % NW;  // this wave copies LPW_HI chunks
+  // this wave's copies of stage st (clamped to the last: the tail copies
+  // are never read) into its slot st % S (chunk c = wave + i NW)
+  auto issue = [&](int st) {
+    const int sl = st % S;
+    st = st < nst ? st : nst - 1;
 #pragma unroll
     for (int i = 0; i < LPW_HI; i++) {
       const int c = wave + i * NW;
@@ -49,46 +57,61 @@ __device__ __forceinline__ void gemm_staged(const float* __restrict__ Lk, const 
       }
     }
   };
+  auto read_quad = [&](int st, int g, f4 (&a)[RT], f4 (&b)[CT]) {
+    const float* __restrict__ slot = ring[st % S];
 #pragma unroll
-  for (int sl = 0; sl < S - 1; sl++) issue(sl < nst ? sl : nst - 1, sl);
+    for (int rt = 0; rt < RT; rt++)
+      a[rt] = *reinterpret_cast<const f4*>(slot + (g * NQB + wr * RT + rt) * 256 + lane * 4);
+#pragma unroll
+    for (int ct = 0; ct < CT; ct++)
+      b[ct] = *reinterpret_cast<const f4*>(slot + (CL + g * CTS + wc * CT + ct) * 256 + lane * 4);
+  };
+  // each tile's quad is a fresh FP32 chain (started from zero) folded into
+  // the FP64 sum as soon as it is done: the fold of one tile has no
+  // dependence on the next tile's MFMAs, so the two overlap
+  auto mfma_quad = [&](const f4 (&a)[RT], const f4 (&b)[CT]) {
+#pragma unroll
+    for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+      for (int ct = 0; ct < CT; ct++) {
+        f4 c = MFMA32(a[rt].x, b[ct].x, ((f4){0, 0, 0, 0}));
+        c = MFMA32(a[rt].y, b[ct].y, c);
+        c = MFMA32(a[rt].z, b[ct].z, c);
+        c = MFMA32(a[rt].w, b[ct].w, c);
+#pragma unroll
+        for (int i = 0; i < 4; i++) acc[rt][ct][i] += (double)c[i];
+      }
+  };
+  // all S slots filled, stage 0 visible
+#pragma unroll
+  for (int st = 0; st < S; st++) issue(st);
+  if (hi)
+    wait_vm_lgkm0<(S - 1) * LPW_HI>();
+  else
+    wait_vm_lgkm0<(S - 1) * LPW_LO>();
+  barrier_only();
+  f4 a0[RT], b0[CT], a1[RT], b1[CT];
+  read_quad(0, 0, a0, b0);
   for (int st = 0; st < nst; st++) {
-    // stage st is in LDS for every wave; every wave is done with slot (st-1)%S
-    if (LPW_HI == LPW_LO || wave < CPS % NW)
+    // the first quad's reads, issued a quad of MFMAs ago, have landed; waiting
+    // here keeps the wait for them from also covering the reads issued next
+    wait_lgkm0();
+    read_quad(st, 1, a1, b1);
+    // the reads go out before the MFMAs that hide them, and the MFMAs before
+    // the wait and the barrier
+    __builtin_amdgcn_sched_barrier(0);
+    mfma_quad(a0, b0);
+    __builtin_amdgcn_sched_barrier(0);
+    // stage st+1 is in LDS for every wave; every wave has read all of stage st
+    if (hi)
       wait_vm_lgkm0<(S - 2) * LPW_HI>();
     else
       wait_vm_lgkm0<(S - 2) * LPW_LO>();
     barrier_only();
-    {
-      // refill the freed slot with stage st + S - 1 (clamped: the tail
-      // copies are never read)
-      const int nx = st + S - 1;
-      issue(nx < nst ? nx : nst - 1, nx % S);
-    }
-    const float* __restrict__ slot = ring[st % S];
-#pragma unroll
-    for (int g = 0; g < G; g++) {
-      f4 a[RT], b[CT];
-#pragma unroll
-      for (int rt = 0; rt < RT; rt++)
-        a[rt] = *reinterpret_cast<const f4*>(slot + (g * NQB + wr * RT + rt) * 256 + lane * 4);
-#pragma unroll
-      for (int ct = 0; ct < CT; ct++)
-        b[ct] = *reinterpret_cast<const f4*>(slot + (CL + g * CTS + wc * CT + ct) * 256 + lane * 4);
-      // each tile's quad is a fresh FP32 chain (started from zero) folded
-      // into the FP64 sum as soon as it is done: the fold of one tile has
-      // no dependence on the next tile's MFMAs, so the two overlap
-#pragma unroll
-      for (int rt = 0; rt < RT; rt++)
-#pragma unroll
-        for (int ct = 0; ct < CT; ct++) {
-          f4 c = MFMA32(a[rt].x, b[ct].x, ((f4){0, 0, 0, 0}));
-          c = MFMA32(a[rt].y, b[ct].y, c);
-          c = MFMA32(a[rt].z, b[ct].z, c);
-          c = MFMA32(a[rt].w, b[ct].w, c);
-#pragma unroll
-          for (int i = 0; i < 4; i++) acc[rt][ct][i] += (double)c[i];
-        }
-    }
+    issue(st + S);
+    read_quad(st + 1, 0, a0, b0);  // (past the last stage: a clamped copy, unused)
+    __builtin_amdgcn_sched_barrier(0);
+    mfma_quad(a1, b1);
     asm volatile("" ::: "memory");
   }
   // the ring shares its LDS with the right-hand side staged next: the tail
