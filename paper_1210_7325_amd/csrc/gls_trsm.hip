@@ -467,12 +467,12 @@ hipError_t launch_trsm_i8(const JobTable& tab, int64_t nslabs, int C, hipStream_
       if (last) k_trsm_last<32, 4, 2, TRSM_DEPTH><<<(unsigned)nslabs, 512, 0, st>>>(tab);
       break;
     case 64:
-      k_trsm<64, 4, 2, TRSM_DEPTH, int8_t><<<(unsigned)nslabs, 512, 0, st>>>(tab);
+      k_trsm<64, 4, 2, TRSM_DEPTH, int8_t, 2, 4><<<(unsigned)nslabs, 512, 0, st>>>(tab);
       if (last) k_trsm_last<64, 4, 2, TRSM_DEPTH><<<(unsigned)nslabs, 512, 0, st>>>(tab);
       break;
     case 128:
-      // staged operands: a 32 x 64 tile per wave fits in registers only
-      // without the register ring
+      // staged operands (64 and 128 columns): a 32 x 64 tile per wave fits
+      // in registers only without the register ring
       k_trsm<128, 4, 2, TRSM_DEPTH, int8_t, 2, 4><<<(unsigned)nslabs, 512, 0, st>>>(tab);
       if (last) k_trsm_last<128, 4, 2, 2><<<(unsigned)nslabs, 512, 0, st>>>(tab);
       break;
