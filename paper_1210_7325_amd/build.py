@@ -46,16 +46,25 @@ GLS_UNITS = ("gls_factor.hip", "gls_fixed.hip", "gls_trsm.hip", "gls_trsm_mixed.
              "gls_assemble.hip", "gls_api.cpp", "gls_io.cpp")
 
 
+def _code_only(text: str) -> str:
+    """C++ source without comments and with whitespace runs collapsed (the
+    sources hold no string literal containing comment markers)."""
+    import re
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def trsm_source_digest() -> str:
     """SHA-256 over everything that decides the FP64 triangular-solve
-    kernel's machine code: its source, the shared device headers and the
-    compiler flags.  Counter readings taken for one digest are stale for
-    any other."""
+    kernel's machine code: its source and the shared device headers (code
+    only: comments and layout do not count) and the compiler flags.  Counter
+    readings taken for one digest are stale for any other."""
     import hashlib
     h = hashlib.sha256()
     for name in ("gls_trsm.hip", "gls_device.h", "gls_internal.h"):
-        with open(os.path.join(CSRC, name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(CSRC, name), encoding="utf-8") as f:
+            h.update(_code_only(f.read()).encode())
     h.update(" ".join(HIP_FLAGS[:-2]).encode())  # flags without the include paths
     return h.hexdigest()
 

@@ -4,16 +4,19 @@
 namespace gls {
 
 // ---------------------------------------------------------------------------
-// a1/a2: blocked lower triangular solve  W = L^{-1} X  (the trsm of Alg. 5,
+// a2: blocked lower triangular solve  W = L^{-1} X  (the trsm of Alg. 5,
 // grouped over many right-hand sides as the paper prescribes)
 //
 // One work-group owns a slab of C columns and walks the row blocks
 // k = 0..K-1 (left-looking):
-//   R_k = X_k - sum_{j<k} L_kj W_j     FP64 MFMA, operands streamed from the
-//                                      packed strip and the slab's own W
+//   R_k = X_k - sum_{j<k} L_kj W_j     FP64 MFMA, operands from the packed
+//                                      strip and the slab's own W (a
+//                                      register ring per wave, or staged
+//                                      through LDS for the whole group)
 //   W_k = inv(L_kk) R_k                FP64 MFMA, R_k staged in LDS
 // The waves split the NB rows of a block (WR ways) and the C columns (WC
-// ways).  X is int8 genotypes (exact in FP64) or FP64 (fixed part).
+// ways).  X is int8 genotypes, exact in FP64.
+
 // True when the last row block's real rows (n - (K-1) NB of them) all lie in
 // the first of the WR wave rows' tiles (RW rows): the rest of that block is
 // padding, whose R and W are zero, and k_trsm_last solves it.
