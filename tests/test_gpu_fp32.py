@@ -73,19 +73,19 @@ def test_fp32_refine_parity(G, n, pL, pR, t, m, block):
     assert err.max() < TOL_FP32_FORM
 
 
-@pytest.mark.parametrize("n,m,block", [(660, 300, 300), (1000, 700, 333), (129, 90, 45),
-                                       (200, 300, 300)])
-def test_fp32_refine_wide_slabs(G, n, m, block):
+@pytest.mark.parametrize("n,m,block,pR", [(660, 300, 300, 1), (1000, 700, 333, 1), (129, 90, 45, 1),
+                                          (200, 300, 300, 1), (400, 60, 60, 4)])
+def test_fp32_refine_wide_slabs(G, n, m, block, pR):
     """128 genotype columns per work-group: within the bound of the oracle
     and the same bits as 64.  n = 660 leaves its last row block of 20 rows
     to the last-block kernel; n = 1000 ends in a partial row block of the
     main kernel; n = 129 and n = 200 have two row blocks; every block ends
-    in a partial slab."""
-    say("fp32 form, 128-column slabs", n, m, block)
-    w, M, XL, Y, XR = problem(n, 3, 1, m, seed=n + 1)
-    B, info = run(G, M, XL, Y, XR, 1, block, slab=128)
-    B64, _ = run(G, M, XL, Y, XR, 1, block, slab=64)
-    ref = orc.gls_sequence(M, XL, XR, Y, 1)
+    in a partial slab; p_R = 4 puts four problems in each 16-column tile."""
+    say("fp32 form, 128-column slabs", n, m, block, pR)
+    w, M, XL, Y, XR = problem(n, 3, pR, m, seed=n + 1)
+    B, info = run(G, M, XL, Y, XR, pR, block, slab=128)
+    B64, _ = run(G, M, XL, Y, XR, pR, block, slab=64)
+    ref = orc.gls_sequence(M, XL, XR, Y, pR)
     assert np.all(info == 0)
     err = orc.relative_error(B, ref)
     say("max rel err", err.max())

@@ -189,29 +189,32 @@ def test_slab_width_choice_is_bitwise_neutral(G, prec):
     c.free()
 
 
-@pytest.mark.parametrize("n,m,block", [(660, 300, 300), (1000, 700, 333), (64, 50, 50),
-                                       (129, 90, 45), (200, 300, 300)])
-def test_wide_slabs_parity(G, n, m, block):
+@pytest.mark.parametrize("n,m,block,pR", [(660, 300, 300, 1), (1000, 700, 333, 1), (64, 50, 50, 1),
+                                          (129, 90, 45, 1), (200, 300, 300, 1), (300, 100, 60, 3),
+                                          (450, 40, 40, 7)])
+def test_wide_slabs_parity(G, n, m, block, pR):
     """128 genotype columns per work-group (operands staged through LDS):
     within the bound of the oracle and the same bits as 64.  n = 660 leaves
     its last row block of 20 rows to the last-block kernel; n = 1000 ends in
     a partial row block of the main kernel; n = 64 has one row block (no
     off-diagonal product), n = 129 two with the second left to the
     last-block kernel, n = 200 two with one stage ring pass; every block
-    ends in a partial slab."""
-    say("128-column slabs", n, m, block)
+    ends in a partial slab.  p_R = 3 and 7: problems of several genotype
+    columns, several problems per 16-column tile of a 128-column slab."""
+    say("128-column slabs", n, m, block, pR)
     from paper_1210_7325_amd import gls
-    w, M, XL, Y, XR = small_problem(n, m=m, seed=n + 3)
+    w, M, XL, Y, XR = small_problem(n, pR=pR, m=m, seed=n + 3)
     c = gls.Cohort(to_dev(M)).whiten_fixed(to_dev(XL), to_dev(Y))
     dXR = to_dev(XR)
     outs = {}
     for C in (128, 64):
         c.set_slab_cols(C)
-        parts = [c.solve_block(dXR[:, a:min(m, a + block)]) for a in range(0, m, block)]
+        parts = [c.solve_block(dXR[:, a * pR:min(m, a + block) * pR], p_R=pR)
+                 for a in range(0, m, block)]
         assert all(np.all(i.cpu().numpy() == 0) for _, i in parts)
         outs[C] = torch.cat([b for b, _ in parts]).cpu().numpy()
     c.free()
-    ref = orc.gls_sequence(M, XL, XR, Y, 1)
+    ref = orc.gls_sequence(M, XL, XR, Y, pR)
     err = orc.relative_error(outs[128], ref)
     say("max rel err", err.max())
     assert err.max() < TOL_B
