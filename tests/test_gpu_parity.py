@@ -168,13 +168,16 @@ def test_deterministic_and_block_independent(G):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32_refine"])
-def test_slab_width_choice_is_bitwise_neutral(G, prec):
+@pytest.mark.parametrize("n", [700, 660])
+def test_slab_width_choice_is_bitwise_neutral(G, prec, n):
     """Automatic per-launch slab width (the default) against every fixed
     width: the same bits, for launches small enough to pick 16 or 32,
-    middling (64) and large enough to pick 128 columns per work-group."""
-    say("slab widths", prec)
+    middling (64) and large enough to pick 128 columns per work-group.
+    n = 660 leaves its last row block to the last-block kernel (in every
+    width), n = 700 does not."""
+    say("slab widths", prec, n)
     from paper_1210_7325_amd import gls
-    w, M, XL, Y, XR = small_problem(700, m=40000)
+    w, M, XL, Y, XR = small_problem(n, m=40000)
     c = gls.Cohort(to_dev(M), precision=prec).whiten_fixed(to_dev(XL), to_dev(Y), intercept_col=0)
     dXR = to_dev(XR)
     widths = (32, 64, 128) if prec == "fp32_refine" else (16, 32, 64, 128)
