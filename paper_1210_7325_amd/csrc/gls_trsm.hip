@@ -24,6 +24,12 @@ __host__ __device__ inline bool last_block_split(int64_t n, int K, int RW) {
   return K > 1 && n - (int64_t)(K - 1) * NB <= RW;
 }
 
+// The last-block kernel always has four wave rows (NB / 4 rows each), so
+// that it sums the last block's GEMM in the same order whatever the slab
+// width (and whatever the main kernel's wave rows): results stay bitwise
+// independent of the width.
+constexpr int LAST_RW = NB / 4;
+
 template <int C, int G>
 constexpr int staged_ring_doubles(int S) { return S * G * (NB / 16 + C / 16) * 128; }
 
@@ -163,8 +169,8 @@ __global__ __launch_bounds__(64 * WR * WC) void k_trsm(const JobTable tab) {
   const int64_t col_base = slab * C + wc * CW;
 
   // the last row block is left to k_trsm_last when all of its real rows
-  // lie in the first wave row's tile
-  const int Kmain = last_block_split(n, K, RW) ? K - 1 : K;
+  // lie in the first of its wave rows' tiles
+  const int Kmain = last_block_split(n, K, LAST_RW) ? K - 1 : K;
   for (int k = 0; k < Kmain; k++) {
     // this block's right-hand side, loaded early and held as loaded (it is
     // consumed after the GEMM).  When the wave's tile lies inside the matrix
@@ -456,13 +462,15 @@ __global__ void k_slab_to_colmajor(const double* __restrict__ W, int C, int64_t 
 
 
 hipError_t launch_trsm_i8(const JobTable& tab, int64_t nslabs, int C, hipStream_t st) {
-  // the last row block goes to k_trsm_last when some job of the table wants
-  // it (WR = 4 wave rows of NB / 4 rows in every configuration)
+  // the last row block goes to k_trsm_last when some job of the table wants it
   bool last = false;
-  for (int i = 0; i < tab.njobs; i++) last = last || last_block_split(tab.j[i].n, tab.j[i].K, NB / 4);
+  for (int i = 0; i < tab.njobs; i++) last = last || last_block_split(tab.j[i].n, tab.j[i].K, LAST_RW);
   switch (C) {
     case 16:
-      k_trsm<16, 4, 1, TRSM_DEPTH, int8_t><<<(unsigned)nslabs, 256, 0, st>>>(tab);
+      // 8 waves of 16 x 16 tiles, so that a slab walks its row blocks with
+      // two waves per SIMD (one wave per SIMD issues FP64 MFMAs at about half
+      // rate); a wave's pair of MFMAs is short, so 8 pairs are kept in flight
+      k_trsm<16, 8, 1, 8, int8_t><<<(unsigned)nslabs, 512, 0, st>>>(tab);
       if (last) k_trsm_last<16, 4, 1, TRSM_DEPTH><<<(unsigned)nslabs, 256, 0, st>>>(tab);
       break;
     case 32:
