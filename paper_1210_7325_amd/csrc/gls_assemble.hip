@@ -322,7 +322,8 @@ __global__ __launch_bounds__(64 * AS_WAVES) void k_assemble_solve(const AsmTable
 // row octets w, w + 8, ... of its wave (one 8-byte load when the column
 // start and the leading dimension allow it, byte loads otherwise and in the
 // tail).  Second pass: (x - s)^T Z as the assembly's products on FP64 MFMA,
-// the A operand built from two genotype bytes per lane and tile.
+// the A operand built from two genotype bytes per lane and tile (taken from
+// one 8-byte load of the octet under the same conditions as the first pass).
 __device__ __forceinline__ void xz_octet(const int8_t* __restrict__ x, int64_t o, int64_t n,
                                          bool vec, int8_t (&b)[8]) {
   const int64_t r0 = 8 * o;
@@ -383,7 +384,17 @@ __global__ __launch_bounds__(64 * AS_WAVES) void k_xz_shift(const XzTable tab) {
     xs[ct] = J.X + (c < J.ncols ? c : col0) * J.ldx;
     sft[ct] = sh[16 * ct + cl];
   }
+  // the lane's two genotypes of an octet (rows 8o + r and 8o + r + 4 of its
+  // column): one 8-byte load of the whole octet (shared by the column's four
+  // lanes) when aligned and inside the column, else two byte loads
+  const bool vec = (reinterpret_cast<uintptr_t>(J.X) % 8 == 0) && (J.ldx % 8 == 0);
   auto loadA = [&](int ct, int64_t o) __attribute__((always_inline)) -> d2 {
+    if (vec && 8 * o + 8 <= n) {
+      const int2 v = *reinterpret_cast<const int2*>(xs[ct] + 8 * o);
+      const double a0 = (double)(int8_t)((v.x >> (8 * r)) & 0xff) - sft[ct];
+      const double a1 = (double)(int8_t)((v.y >> (8 * r)) & 0xff) - sft[ct];
+      return d2{a0, a1};
+    }
     const int64_t r0 = 8 * o + r, r1 = r0 + 4;
     const double a0 = r0 < n ? (double)xs[ct][r0] - sft[ct] : 0.0;
     const double a1 = r1 < n ? (double)xs[ct][r1] - sft[ct] : 0.0;
