@@ -104,7 +104,7 @@ int gls_solve_block(gls_handle h, int64_t nsnp, int64_t p_R,
                     int32_t* info);
 
 /* Pre-size the workspace for blocks of up to max_cols = nsnp*p_R genotype
- * columns.  Synchronous allocation. */
+ * columns (rounded up to a multiple of 128).  Synchronous allocation. */
 int gls_reserve(gls_handle h, int64_t max_cols);
 
 /* Release the handle and all device memory it owns (after synchronizing
@@ -164,7 +164,10 @@ int gls_whiten_block(gls_handle h, int64_t ncols, const int8_t* X, int64_t ldx,
  * number at most one per compute unit, else 128 — a slab's walk down the
  * row blocks takes about the same time whatever runs beside it, so small
  * launches finish sooner in narrow slabs and full launches run best in wide
- * ones.  Other values return -2.  A performance knob only: every column is
+ * ones — except that 64 is kept when a 128-column slab of the launch's
+ * largest cohort would take longer than the launch's 64-column slabs spread
+ * over the compute units (launches mixing cohorts of different n).  Other
+ * values return -2.  A performance knob only: every column is
  * whitened by the same sequence of operations whatever its slab, so results
  * are bitwise independent of it.  Items of one gls_solve_multi call must
  * share the setting. */
