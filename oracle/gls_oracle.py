@@ -97,48 +97,6 @@ def fixed_blocks(L, XL, Y):
     return WL, yt, WL.T @ WL, WL.T @ yt
 
 
-def hp_gwas_host(M, XL, XR, Y, p_R: int = 1, block: int = 4096, L=None) -> np.ndarray:
-    """The paper's fast algorithm (Sec. 2, Alg. 5 "hp-gwas") on the CPU, for
-    timing the method itself on the host cores (a context figure beside the
-    oracle, which computes the definition instead).
-
-    Steps in the paper's order: the Cholesky factor of M (potrf); W_L =
-    L^{-1} X_L and ytil = L^{-1} y (trsm, trsv); S_TL = W_L^T W_L and
-    C_T = W_L^T ytil (syrk, gemv); then per block of SNPs one triangular solve
-    W_R = L^{-1} X_R of the whole block (the grouped trsm), and per problem
-    S_BL = W_R_i^T W_L, S_BR = W_R_i^T W_R_i, C_B = W_R_i^T ytil, assembled
-    with S_TL, C_T as in Fig. 1 and solved.  Library primitives: Cholesky,
-    triangular solve, (batched) matrix products and a batched small dense
-    solve for the p x p systems.  Same output convention as gls_sequence."""
-    Y = np.asarray(Y, dtype=np.float64)
-    if Y.ndim == 1:
-        Y = Y[:, None]
-    if L is None:
-        L = cholesky_lower(M)
-    WL, yt, STL, CT = fixed_blocks(L, XL, Y)
-    n, p_L = WL.shape
-    t = yt.shape[1]
-    m = XR.shape[1] // p_R
-    p = p_L + p_R
-    out = np.empty((m, t, p), dtype=np.float64)
-    for a in range(0, m, block):
-        b = min(m, a + block)
-        k = b - a
-        WR = whiten(L, np.asarray(XR[:, a * p_R:b * p_R], dtype=np.float64))
-        Wk = WR.T.reshape(k, p_R, n)                  # W_R_i^T, (k, p_R, n)
-        S = np.empty((k, p, p))
-        S[:, :p_L, :p_L] = STL
-        SBL = Wk @ WL                                 # (k, p_R, p_L)
-        S[:, p_L:, :p_L] = SBL
-        S[:, :p_L, p_L:] = SBL.transpose(0, 2, 1)
-        S[:, p_L:, p_L:] = Wk @ Wk.transpose(0, 2, 1)
-        c = np.empty((k, p, t))
-        c[:, :p_L] = CT
-        c[:, p_L:] = Wk @ yt
-        out[a:b] = np.linalg.solve(S, c).transpose(0, 2, 1)
-    return out
-
-
 def relative_error(b_hat, b_ref) -> np.ndarray:
     """Per problem and phenotype: ||b_hat - b_ref||_inf / ||b_ref||_inf."""
     b_hat = np.asarray(b_hat, dtype=np.float64)

@@ -93,23 +93,41 @@ def test_fp32_refine_wide_slabs(G, n, m, block, pR):
     assert np.array_equal(B, B64)
 
 
-def test_fp32_refine_stress_conditioning(G):
-    """q = n/4, h = 0.99: kappa(M) ~ 800 (the workloads have kappa ~ 4-10).
-    The FP32-rounded operands of the off-diagonal products leave an error
-    in the whitened genotypes that grows with kappa(L) = sqrt(kappa(M)), and
-    the refinement cannot remove the part that enters S_BR; at this
-    conditioning the bound is 1e-7 (measured ~4e-8), against 1e-8 at the
-    workloads' conditioning."""
-    say("fp32 stress")
-    w, M, XL, Y, XR = problem(1200, 3, 1, 400, q=300, h=0.99, seed=7)
+# The FP32_REFINE form's bound on the max relative error of b_i as a function
+# of the conditioning of M (the same table is in include/gls.h): the
+# FP32-rounded operands of the off-diagonal products leave an error in the
+# whitened genotypes that grows with kappa(L) = sqrt(kappa(M)), and the
+# refinement cannot remove the part that enters S_BR.
+FP32_BOUND_BY_KAPPA = ((10.0, 1e-8), (60.0, 3e-8), (250.0, 6e-8), (1000.0, 1e-7))
+
+
+def fp32_bound(kappa):
+    for k, b in FP32_BOUND_BY_KAPPA:
+        if kappa <= k:
+            return b
+    raise ValueError(f"no bound stated for kappa(M) = {kappa}")
+
+
+@pytest.mark.parametrize("q_frac,h,kappa_lo,kappa_hi", [
+    (2.0, 0.5, 3.0, 5.0), (0.25, 0.85, 40.0, 60.0), (0.25, 0.96, 150.0, 250.0),
+    (0.25, 0.99, 600.0, 1000.0)])
+def test_fp32_refine_error_vs_conditioning(G, q_frac, h, kappa_lo, kappa_hi):
+    """M = h Phi + (1-h) I + 1e-3 I with Phi of rank q: q = 2n, h = 0.5 is the
+    workloads' conditioning (kappa ~ 3.6); q = n/4 with h = 0.85, 0.96, 0.99
+    gives kappa ~ 50, 200, 800.  1,000 problems at n = 1,200 against the
+    oracle, asserting the stated bound for that kappa."""
+    n = 1200
+    w, M, XL, Y, XR = problem(n, 3, 1, 1000, q=int(q_frac * n), h=h, seed=7)
     ev = np.linalg.eigvalsh(M)
-    say("kappa(M)", ev[-1] / ev[0])
-    assert ev[-1] / ev[0] > 500
-    B, info = run(G, M, XL, Y, XR, 1, 400)
+    kappa = ev[-1] / ev[0]
+    say("kappa(M)", kappa)
+    assert kappa_lo < kappa < kappa_hi
+    B, info = run(G, M, XL, Y, XR, 1, 512, slab=0)
     ref = orc.gls_sequence(M, XL, XR, Y, 1)
     err = orc.relative_error(B, ref)
-    say("stress max rel err", err.max())
-    assert np.all(info == 0) and err.max() < 1e-7
+    say(f"kappa {kappa:.1f}: max rel err {err.max():.3e}, p99.99 {np.quantile(err, 0.9999):.3e}, "
+        f"bound {fp32_bound(kappa):.0e}")
+    assert np.all(info == 0) and err.max() < fp32_bound(kappa)
 
 
 def test_fp32_whitening_error_is_fp32_level(G):
@@ -172,3 +190,13 @@ def test_fp32_refine_full_n_sampled(G):
     err = orc.relative_error(B, ref)
     say("fp32 full n sampled max rel err", err.max())
     assert err.max() < TOL_FP32_FORM
+    # every problem against the FP64 path, itself checked against the oracle
+    # on the same sample (within 1e-12)
+    B64 = torch.empty_like(Bout)
+    bench.run_step(G, torch, torch.from_numpy(M).cuda(), to_dev(XL), to_dev(Y), dXR, w, m,
+                   w.block, [stream], 0, B64, info, batch=2, precision="fp64")
+    torch.cuda.synchronize()
+    assert orc.relative_error(B64[torch.from_numpy(idx).cuda()].cpu().numpy(), ref).max() < 1e-12
+    err_all = orc.relative_error(Bout.cpu().numpy(), B64.cpu().numpy())
+    say("fp32 full n, all", m, "problems against fp64: max rel err", err_all.max())
+    assert err_all.max() < TOL_FP32_FORM

@@ -93,6 +93,98 @@ def test_normal_equation_residual_vanishes():
     assert res.max() < 1e-13
 
 
+def _exact_norm_inf(A):
+    """Max row sum of absolute values, exact (Fractions)."""
+    return max(sum(abs(v) for v in row) for row in A)
+
+
+def _residual_vs_exact(resid_fn):
+    """Checks a normal-equation residual function against exact arithmetic on
+    the golden cases; returns (largest value at the exact b, largest
+    relative mismatch at perturbed and wrong-model b, smallest exact value).
+
+    With b_i = b*_i + delta (b*_i the exact solution), the residual of the
+    normal equations is X_i^T M^-1 (y - X_i b_i) = -S_i delta exactly, with
+    S_i = X_i^T M^-1 X_i: its value is computed here from S_i and delta in
+    rationals, not by evaluating the residual's own formula."""
+    from oracle.exact import inverse, matmul, to_fractions, transpose
+    doc = json.load(open(os.path.join(HERE, "golden", "tiny_exact.json")))
+    rng = np.random.default_rng(21)
+    at_exact, mismatch, smallest = 0.0, 0.0, np.inf
+    for c in doc["cases"]:
+        M, XL, XR, Y = (np.array(c[k], dtype=np.float64) for k in ("M", "XL", "XR", "Y"))
+        p_R, t = c["p_R"], c["t"]
+        bstar = [[[_frac(v) for v in bj] for bj in bi] for bi in c["b"]]
+        B0 = np.array([[[float(v) for v in bj] for bj in bi] for bi in bstar])
+        at_exact = max(at_exact, float(np.max(resid_fn(M, XL, XR, Y, B0, p_R))))
+        # the wrong model: b solved with M instead of M^-1
+        Bw = np.empty_like(B0)
+        for i in range(B0.shape[0]):
+            Xi = np.hstack([XL, XR[:, i * p_R:(i + 1) * p_R]])
+            Bw[i] = np.linalg.solve(Xi.T @ M @ Xi, Xi.T @ M @ Y).T
+        Bp = B0 * (1.0 + 1e-6 * rng.standard_normal(B0.shape))
+        Mi = inverse(to_fractions(M))
+        XLf, XRf, Yf = to_fractions(XL), to_fractions(XR), to_fractions(Y)
+        n = len(XLf)
+        for Bt in (Bp, Bw):
+            got = resid_fn(M, XL, XR, Y, Bt, p_R)
+            for i in range(Bt.shape[0]):
+                Xi = [XLf[r] + XRf[r][i * p_R:(i + 1) * p_R] for r in range(n)]
+                XtMi = matmul(transpose(Xi), Mi)
+                S = matmul(XtMi, Xi)
+                for j in range(t):
+                    bt = [Fraction(float(v)) for v in Bt[i, j]]
+                    delta = [[bt[r] - bstar[i][j][r]] for r in range(len(bt))]
+                    res = [abs(v[0]) for v in matmul(S, delta)]
+                    scale = _exact_norm_inf(XtMi) * max(abs(Yf[r][j]) for r in range(n)) \
+                        + _exact_norm_inf(S) * max(abs(v) for v in bt)
+                    want = float(max(res) / scale)
+                    smallest = min(smallest, want)
+                    mismatch = max(mismatch, abs(float(got[i, j]) - want) / want)
+    return at_exact, mismatch, smallest
+
+
+def test_normal_equation_residual_pinned_by_exact_rationals():
+    """The exact b* (rounded to FP64) gives <= 1e-13; a perturbed b
+    (relative 1e-6) and the b of the wrong model (M in place of M^-1) give
+    the exact relative residual (to 1e-6 of its value), far above 1e-8."""
+    at_exact, mismatch, smallest = _residual_vs_exact(orc.normal_equation_residual)
+    assert at_exact <= 1e-13
+    assert smallest > 1e-9
+    assert mismatch <= 1e-6
+
+
+def test_normal_equation_residual_planted_mistakes():
+    """Plausible mistakes in the residual, planted in copies on the CPU, fail
+    the exact pin: a residual that is always zero, M not inverted, and a
+    scale missing its ||S|| ||b|| term."""
+    import scipy.linalg as sla
+
+    def variant(kind):
+        def fn(M, XL, XR, Y, B, p_R=1):
+            Y = np.asarray(Y, dtype=np.float64).reshape(M.shape[0], -1)
+            lu = sla.lu_factor(M)
+            res = np.empty(B.shape[:2])
+            for i in range(B.shape[0]):
+                Xi = np.hstack([XL, np.asarray(XR[:, i * p_R:(i + 1) * p_R], dtype=np.float64)])
+                Wt = (M @ Xi).T if kind == "M_not_inverted" else sla.lu_solve(lu, Xi).T
+                S = Wt @ Xi
+                for j in range(Y.shape[1]):
+                    r = Wt @ (Y[:, j] - Xi @ B[i, j])
+                    scale = np.linalg.norm(Wt, np.inf) * np.linalg.norm(Y[:, j], np.inf)
+                    if kind != "scale_term_dropped":
+                        scale += np.linalg.norm(S, np.inf) * np.linalg.norm(B[i, j], np.inf)
+                    res[i, j] = 0.0 if kind == "zero" else np.linalg.norm(r, np.inf) / scale
+            return res
+        return fn
+
+    at_exact, mismatch, _ = _residual_vs_exact(variant("none"))
+    assert at_exact <= 1e-13 and mismatch <= 1e-6
+    for kind in ("zero", "M_not_inverted", "scale_term_dropped"):
+        at_exact, mismatch, _ = _residual_vs_exact(variant(kind))
+        assert at_exact > 1e-13 or mismatch > 1e-3, kind
+
+
 # --- invariances of Eq. (1) ---------------------------------------------------
 def test_invariances():
     rng = np.random.default_rng(6)
@@ -179,12 +271,13 @@ def test_cross_routes_agree():
 
 @pytest.mark.parametrize("p_R,t,block", [(1, 1, 4), (2, 3, 5), (3, 2, 100)])
 def test_host_hp_gwas_matches_definition(p_R, t, block):
-    """The oracle's host version of Alg. 5 (timed as context by the
-    benchmark) reaches the definition's b_i, across block boundaries."""
+    """The benchmark's host version of Alg. 5 (timed as a context figure)
+    reaches the definition's b_i, across block boundaries."""
+    import bench
     rng = np.random.default_rng(11 + p_R)
     M, XL, XR, Y = rand_problem(rng, n=60, p_L=3, p_R=p_R, m=11, t=t)
     ref = orc.gls_sequence(M, XL, XR, Y, p_R)
-    got = orc.hp_gwas_host(M, XL, XR, Y, p_R, block=block)
+    got = bench.host_alg5(M, XL, XR, Y, p_R, block=block)
     assert got.shape == ref.shape
     assert maxrel(got, ref) < 1e-11
 
