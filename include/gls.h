@@ -62,7 +62,8 @@ enum {
   GLS_E_HIP = 4,         /* a HIP runtime call failed                     */
   GLS_E_UNSUPPORTED = 5, /* valid but unsupported request                 */
   GLS_E_IO = 6,          /* a file could not be opened or read            */
-  GLS_E_ABORTED = 7      /* a stream callback returned nonzero            */
+  GLS_E_ABORTED = 7,     /* a stream callback returned nonzero            */
+  GLS_E_TOO_LARGE = 8    /* block exceeds gls_solve_block_noalloc's scratch */
 };
 
 /* Factor M = L L^T (Cholesky; the potrf of Alg. 3-5, done once per
@@ -102,6 +103,28 @@ int gls_whiten_fixed(gls_handle h, int64_t p_L, const double* X_L, int64_t ldx,
 int gls_solve_block(gls_handle h, int64_t nsnp, int64_t p_R,
                     const int8_t* X_R, int64_t ldxr, double* B, int64_t ldb,
                     int32_t* info);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation and results as gls_solve_block, bit for bit, but the
+ * whitened-column workspace is a fixed array of GLS_NOALLOC_SCRATCH_BYTES in
+ * the library's device code, one per device, held from its first use until
+ * the process ends, instead of the handle's own (grown) workspace.  The call
+ * allocates and frees nothing.  The block may need at most that many bytes:
+ * W is 8 * n_pad * c bytes (n_pad = n rounded up to a multiple of 128,
+ * c = nsnp*p_R rounded up to a multiple of 128), and the FP32_REFINE form
+ * adds 4 * n_pad * c + 8 * c + 224 * c bytes (each part rounded up to 256
+ * bytes); e.g. at n = 10,000 up to 1,536 columns (FP64) or 1,024 (FP32_REFINE).
+ * A larger block returns GLS_E_TOO_LARGE before any device work.  The first
+ * call on a device looks up the array's address there (hipGetSymbolAddress,
+ * with that device made current for the lookup).  Every call on one device
+ * uses the same array: calls whose work overlaps on the device (for example
+ * on different streams, or from different handles) race and give undefined
+ * results; calls ordered on one stream are safe.  Argument checks and the
+ * other error codes as gls_solve_block.  Asynchronous on h's stream. */
+#define GLS_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+int gls_solve_block_noalloc(gls_handle h, int64_t nsnp, int64_t p_R, const int8_t* X_R,
+                            int64_t ldxr, double* B, int64_t ldb, int32_t* info);
 
 /* Pre-size the workspace for blocks of up to max_cols = nsnp*p_R genotype
  * columns (rounded up to a multiple of 128).  Synchronous allocation. */

@@ -43,7 +43,7 @@ def _run(cmd):
 
 # translation units of libgls.so, one per step of the path (plus the C ABI)
 GLS_UNITS = ("gls_factor.hip", "gls_fixed.hip", "gls_trsm.hip", "gls_trsm_mixed.hip",
-             "gls_assemble.hip", "gls_api.cpp", "gls_io.cpp")
+             "gls_assemble.hip", "gls_api.cpp", "gls_io.cpp", "gls_noalloc.hip")
 
 
 def _code_only(text: str) -> str:

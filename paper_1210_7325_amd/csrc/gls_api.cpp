@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "gls.h"
+#include "gls_host.h"
 #include "gls_internal.h"
 
 using namespace gls;
@@ -35,6 +36,7 @@ struct Cohort {
   double* CT = nullptr;        // pL x t
   double* Z = nullptr;         // FP32_REFINE: row-major n_pad x (pL+t), M^{-1}[X_L | Y]
   int cus = 256;               // compute units of the device the cohort lives on
+  int device = 0;              // the device current at gls_factor
 };
 
 }  // namespace
@@ -126,7 +128,12 @@ int ensure_workspace(gls_handle h, int64_t ncols) {
   return GLS_OK;
 }
 
-JobDesc make_job(gls_handle h, int64_t slab0, int64_t ncols, const void* X, int64_t ldx) {
+// The workspace a launch writes: the handle's own, or caller-provided memory
+// (the no-allocation entry point).
+Workspace own_workspace(gls_handle h) { return Workspace{h->W, h->W32, h->shift, h->XZ}; }
+
+JobDesc make_job(gls_handle h, const Workspace& ws, int64_t slab0, int64_t ncols, const void* X,
+                 int64_t ldx) {
   JobDesc j;
   j.slab0 = slab0;
   j.n = h->c->n;
@@ -135,15 +142,16 @@ JobDesc make_job(gls_handle h, int64_t slab0, int64_t ncols, const void* X, int6
   j.ldx = ldx;
   j.Lstrips = h->c->Lstrips;
   j.LinvP = h->c->LinvP;
-  j.W = h->W;
+  j.W = ws.W;
   j.K = h->c->K;
   j.Lstrips32 = h->c->Lstrips32;
-  j.W32 = h->W32;
-  j.shift = h->shift;
+  j.W32 = ws.W32;
+  j.shift = ws.shift;
   return j;
 }
 
-XzDesc make_xz(gls_handle h, int64_t grp0, int64_t ncols, const int8_t* X, int64_t ldx) {
+XzDesc make_xz(gls_handle h, const Workspace& ws, int64_t grp0, int64_t ncols, const int8_t* X,
+               int64_t ldx) {
   XzDesc x;
   x.grp0 = grp0;
   x.n = h->c->n;
@@ -151,19 +159,19 @@ XzDesc make_xz(gls_handle h, int64_t grp0, int64_t ncols, const int8_t* X, int64
   x.X = X;
   x.ldx = ldx;
   x.Z = h->c->Z;
-  x.shift = h->shift;
-  x.XZ = h->XZ;
+  x.shift = ws.shift;
+  x.XZ = ws.XZ;
   x.ldf = (int)(h->c->pL + h->c->t);
   return x;
 }
 
-AsmDesc make_asm(gls_handle h, int C, int64_t grp0, int64_t nsnp, int64_t pR, double* B, int64_t ldb,
-                 int32_t* info) {
+AsmDesc make_asm(gls_handle h, const Workspace& ws, int C, int64_t grp0, int64_t nsnp, int64_t pR,
+                 double* B, int64_t ldb, int32_t* info) {
   AsmDesc a;
   a.grp0 = grp0;
   a.n = h->c->n;
   a.n_pad = h->c->n_pad;
-  a.W = h->W;
+  a.W = ws.W;
   a.F = h->c->F;
   a.STL = h->c->STL;
   a.CT = h->c->CT;
@@ -175,8 +183,8 @@ AsmDesc make_asm(gls_handle h, int C, int64_t grp0, int64_t nsnp, int64_t pR, do
   a.pL = (int)h->c->pL;
   a.pR = (int)pR;
   a.t = (int)h->c->t;
-  a.shift = h->shift;
-  a.XZ = h->XZ;
+  a.shift = ws.shift;
+  a.XZ = ws.XZ;
   a.icol = (int)h->c->icol;
   return a;
 }
@@ -255,11 +263,17 @@ int slab_cols_for(const gls_work* items, int64_t count) {
 
 // Launch the kernels of up to MAX_INLINE_JOBS checked work items (same slab
 // width setting and precision) on stream st; timing events go through
-// handle th.
-int launch_items(const gls_work* items, int64_t count, hipStream_t st, gls_handle th) {
-  for (int64_t i = 0; i < count; i++) {
-    int rc = ensure_workspace(items[i].h, items[i].nsnp * items[i].p_R);
-    if (rc) return rc;
+// handle th (none if th is NULL).  ws: the workspace of a single item, or
+// NULL for each item's own (grown here when too small).
+int launch_items(const gls_work* items, int64_t count, hipStream_t st, gls_handle th,
+                 const Workspace* ws = nullptr) {
+  if (!ws) {
+    for (int64_t i = 0; i < count; i++) {
+      int rc = ensure_workspace(items[i].h, items[i].nsnp * items[i].p_R);
+      if (rc) return rc;
+    }
+  } else if (count != 1) {
+    return GLS_E_UNSUPPORTED;
   }
   const int C = slab_cols_for(items, count);
   const bool refine = items[0].h->c->prec == GLS_FP32_REFINE;
@@ -272,19 +286,20 @@ int launch_items(const gls_work* items, int64_t count, hipStream_t st, gls_handl
     const gls_work& w = items[i];
     if (w.nsnp == 0) continue;
     const int64_t ncols = w.nsnp * w.p_R;
+    const Workspace wsi = ws ? *ws : own_workspace(w.h);
     if (refine) {
-      xt.j[xt.njobs++] = make_xz(w.h, xgroups, ncols, w.X_R, w.ldxr);
+      xt.j[xt.njobs++] = make_xz(w.h, wsi, xgroups, ncols, w.X_R, w.ldxr);
       xgroups += (ncols + AS_GROUP_COLS - 1) / AS_GROUP_COLS;
     }
-    tab.j[tab.njobs++] = make_job(w.h, slabs, ncols, w.X_R, w.ldxr);
+    tab.j[tab.njobs++] = make_job(w.h, wsi, slabs, ncols, w.X_R, w.ldxr);
     slabs += (ncols + C - 1) / C;
-    at.j[at.njobs++] = make_asm(w.h, C, groups, w.nsnp, w.p_R, w.B, w.ldb, w.info);
+    at.j[at.njobs++] = make_asm(w.h, wsi, C, groups, w.nsnp, w.p_R, w.B, w.ldb, w.info);
     const int64_t per_group = (AS_GROUP_COLS / 16) * (16 / w.p_R);  // problems per assembly work-group
     groups += (w.nsnp + per_group - 1) / per_group;
   }
   if (tab.njobs == 0) return GLS_OK;
-  hipStream_t keep = th->stream;
-  th->stream = st;  // timing events go to the launch stream
+  hipStream_t keep = th ? th->stream : nullptr;
+  if (th) th->stream = st;  // timing events go to the launch stream
   hipError_t e = hipSuccess;
   if (refine) {
     TimedScope tx(th, 1);
@@ -298,11 +313,54 @@ int launch_items(const gls_work* items, int64_t count, hipStream_t st, gls_handl
     TimedScope t1(th, 1);
     e = launch_assemble_solve(at, groups, refine, st);
   }
-  th->stream = keep;
+  if (th) th->stream = keep;
   return hip_code(e);
 }
 
 }  // namespace
+
+namespace gls {
+
+size_t workspace_bytes(gls_handle h, int64_t ncols) {
+  const size_t cols = (size_t)round_up(std::max<int64_t>(ncols, 1), MAX_C);
+  const size_t n_pad = (size_t)h->c->n_pad;
+  size_t b = round_up((int64_t)(n_pad * cols * sizeof(double)), 256);
+  if (h->c->prec == GLS_FP32_REFINE) {
+    b += round_up((int64_t)(n_pad * cols * sizeof(float)), 256);
+    b += round_up((int64_t)(cols * sizeof(double)), 256);
+    b += round_up((int64_t)(cols * (MAXP + MAXT) * sizeof(double)), 256);
+  }
+  return b;
+}
+
+int handle_device(gls_handle h) { return h->c->device; }
+
+int solve_block_in(gls_handle h, int64_t nsnp, int64_t p_R, const int8_t* X_R, int64_t ldxr,
+                   double* B, int64_t ldb, int32_t* info, void* scratch, size_t scratch_bytes) {
+  int rc = check_block(h, nsnp, p_R, X_R, ldxr, B, ldb, 2);
+  if (rc) return rc;
+  if (nsnp == 0) return GLS_OK;
+  const int64_t ncols = nsnp * p_R;
+  if (workspace_bytes(h, ncols) > scratch_bytes) return GLS_E_TOO_LARGE;
+  // carve the workspace out of the caller's memory, in the order and with the
+  // 256-byte alignment workspace_bytes counts
+  const size_t cols = (size_t)round_up(std::max<int64_t>(ncols, 1), MAX_C);
+  const size_t n_pad = (size_t)h->c->n_pad;
+  char* p = static_cast<char*>(scratch);
+  Workspace ws{reinterpret_cast<double*>(p), nullptr, nullptr, nullptr};
+  p += round_up((int64_t)(n_pad * cols * sizeof(double)), 256);
+  if (h->c->prec == GLS_FP32_REFINE) {
+    ws.W32 = reinterpret_cast<float*>(p);
+    p += round_up((int64_t)(n_pad * cols * sizeof(float)), 256);
+    ws.shift = reinterpret_cast<double*>(p);
+    p += round_up((int64_t)(cols * sizeof(double)), 256);
+    ws.XZ = reinterpret_cast<double*>(p);
+  }
+  gls_work w{h, nsnp, p_R, X_R, ldxr, B, ldb, info};
+  return launch_items(&w, 1, h->stream, nullptr, &ws);
+}
+
+}  // namespace gls
 
 extern "C" {
 
@@ -316,6 +374,7 @@ const char* gls_strerror(int code) {
     case GLS_E_UNSUPPORTED: return "unsupported request";
     case GLS_E_IO: return "file could not be opened or read";
     case GLS_E_ABORTED: return "a stream callback asked to stop";
+    case GLS_E_TOO_LARGE: return "block too large for the fixed scratch of the no-allocation entry point";
     default: return code < 0 ? "invalid argument" : "unknown error";
   }
 }
@@ -356,8 +415,8 @@ int gls_factor(gls_handle* out, int64_t n, const double* M, int64_t ldm, int pre
   c->K = (int)((n + NB - 1) / NB);
   {
     int dev = 0, cus = 0;
-    if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+    if (hipGetDevice(&dev) == hipSuccess) c->device = dev;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
       c->cus = cus;
     (void)hipGetLastError();
   }
@@ -562,7 +621,7 @@ int gls_whiten_block(gls_handle h, int64_t ncols, const int8_t* X, int64_t ldx, 
   if (rc) return rc;
   JobTable tab;
   tab.njobs = 1;
-  tab.j[0] = make_job(h, 0, ncols, X, ldx);
+  tab.j[0] = make_job(h, own_workspace(h), 0, ncols, X, ldx);
   const gls_work item{h, ncols, 1, X, ldx, nullptr, 0, nullptr};
   const int C = slab_cols_for(&item, 1);
   TimedScope t0(h, 0);

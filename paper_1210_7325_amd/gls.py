@@ -28,9 +28,12 @@ GLS_FP32_REFINE = 1
 PRECISIONS = {"fp64": GLS_FP64, "fp32_refine": GLS_FP32_REFINE}
 
 GLS_OK, GLS_E_NOT_SPD, GLS_E_STATE, GLS_E_OOM, GLS_E_HIP, GLS_E_UNSUPPORTED = 0, 1, 2, 3, 4, 5
-GLS_E_IO, GLS_E_ABORTED = 6, 7
+GLS_E_IO, GLS_E_ABORTED, GLS_E_TOO_LARGE = 6, 7, 8
+# fixed device scratch of gls_solve_block_noalloc (GLS_NOALLOC_SCRATCH_BYTES)
+NOALLOC_SCRATCH_BYTES = 128 << 20
 
-EXPORTS = ("gls_factor", "gls_whiten_fixed", "gls_solve_block", "gls_reserve", "gls_free",
+EXPORTS = ("gls_factor", "gls_whiten_fixed", "gls_solve_block", "gls_solve_block_noalloc",
+           "gls_reserve", "gls_free",
            "gls_fork", "gls_set_stream", "gls_footprint_bytes", "gls_last_info",
            "gls_strerror", "gls_copy_factor", "gls_copy_fixed", "gls_whiten_block",
            "gls_solve_multi", "gls_set_slab_cols", "gls_set_kernel_timing", "gls_kernel_time",
@@ -75,6 +78,7 @@ def lib() -> ctypes.CDLL:
             "gls_factor": (_int, [ctypes.POINTER(_p), _i64, _p, _i64, _int, _p]),
             "gls_whiten_fixed": (_int, [_p, _i64, _p, _i64, _i64, _p, _i64, _i64]),
             "gls_solve_block": (_int, [_p, _i64, _i64, _p, _i64, _p, _i64, _p]),
+            "gls_solve_block_noalloc": (_int, [_p, _i64, _i64, _p, _i64, _p, _i64, _p]),
             "gls_reserve": (_int, [_p, _i64]),
             "gls_free": (None, [_p]),
             "gls_fork": (_int, [_p, _p, ctypes.POINTER(_p)]),
@@ -133,6 +137,10 @@ def gls_whiten_fixed(h, p_L, X_L, ldx, t, Y, ldy, intercept_col) -> int:
 
 def gls_solve_block(h, nsnp, p_R, X_R, ldxr, B, ldb, info) -> int:
     return lib().gls_solve_block(h, nsnp, p_R, X_R, ldxr, B, ldb, info)
+
+
+def gls_solve_block_noalloc(h, nsnp, p_R, X_R, ldxr, B, ldb, info) -> int:
+    return lib().gls_solve_block_noalloc(h, nsnp, p_R, X_R, ldxr, B, ldb, info)
 
 
 def gls_reserve(h, max_cols) -> int:

@@ -43,6 +43,7 @@ def test_argument_validation_without_device():
     # NULL handles
     assert L.gls_whiten_fixed(None, 3, 1, 10, 1, 1, 10, 0) == -1
     assert L.gls_solve_block(None, 5, 1, 1, 10, 1, 4, None) == -1
+    assert L.gls_solve_block_noalloc(None, 5, 1, 1, 10, 1, 4, None) == -1
     assert L.gls_reserve(None, 10) == -1
     assert L.gls_set_stream(None, None) == -1
     assert L.gls_copy_factor(None, 1, 10) == -1
@@ -62,9 +63,9 @@ def test_argument_validation_without_device():
 
 
 def test_strerror_codes():
-    for code in range(0, 8):
+    for code in range(0, 9):
         assert gls.strerror(code) != "unknown error"
-    assert gls.strerror(8) == "unknown error"
+    assert gls.strerror(9) == "unknown error"
     assert gls.strerror(-3) == "invalid argument"
     assert "positive definite" in gls.strerror(gls.GLS_E_NOT_SPD)
 
