@@ -123,11 +123,23 @@ def build_c_check() -> str:
     return out
 
 
+def build_mfma_valu_bench() -> str:
+    """The issue-rate measurement of MFMAs mixed with VALU instructions (a
+    measurement program for the FP32_REFINE solve's ceiling, not part of
+    the library)."""
+    out = os.path.join(PKG, "mfma_valu_bench")
+    tmp = out + ".tmp"
+    _run([HIPCC, "-x", "hip", *HIP_FLAGS, os.path.join(CSRC, "mfma_valu_bench.hip"), "-o", tmp])
+    os.replace(tmp, out)
+    return out
+
+
 def build_all() -> None:
     build_gen()
     build_gen_dev()
     build_gls()
     build_c_check()
+    build_mfma_valu_bench()
 
 
 if __name__ == "__main__":
