@@ -39,7 +39,7 @@ PEAK_HBM_GBS = 8000.0
 # cores (Table 3): 816 s, i.e. 1,225 solves/s
 PAPER_BI_PER_S = 1_000_000 / 816.0
 WORKLOADS = {"scale": dg.SCALE, "mixed": dg.MIXED, "stream": dg.STREAM, "serve": dg.SERVE_BASE,
-             "ablation": dg.SCALE}
+             "ablation": dg.SCALE, "phenotypes": dg.PHENO}
 
 
 def log(*a):
@@ -555,6 +555,124 @@ def ablation_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def phenotypes_bench(args):
+    """Phenotypes with distinct covariance matrices (the phenotype index of
+    Eq. (1) with its own M_j): t = 4 phenotypes, M_j = h_j Phi + (1 - h_j) I
+    + 1e-3 I (h_j = 0.2, 0.4, 0.6, 0.8), n = 10^4, p = 4, m = 131,072 SNPs
+    shared by all phenotypes.  One handle per M_j (factor and fixed part
+    resident); each launch solves `batch` blocks of 4096 SNPs for every
+    phenotype (gls_solve_multi items sharing the X_R block).  One step =
+    the t factorizations, fixed parts and all t*m problems.  Rate: b_ij/s."""
+    import scipy.linalg as sla
+    import torch
+    from oracle import gls_oracle as orc
+    from paper_1210_7325_amd import gls
+    w = dg.PHENO
+    hs = dg.PHENO_H
+    m = args.m or w.m
+    block = args.block or w.block
+    torch.cuda.set_device(0)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    t0 = time.time()
+    phi = dg.make_phi(w)
+    Ms = [dg.make_M(w, phi, h=h) for h in hs]
+    XL, Y = dg.make_XL(w), dg.make_Y(w)
+    log(f"M_1..M_{len(hs)} built (n={w.n}, q={w.q}) in {time.time() - t0:.1f}s")
+    dMs = [torch.from_numpy(M).cuda() for M in Ms]
+    dXL = torch.from_numpy(np.asfortranarray(XL)).cuda()
+    dYs = [torch.from_numpy(np.asfortranarray(Y[:, j:j + 1])).cuda() for j in range(len(hs))]
+    dXR = upload_genotypes(torch, w, m)
+    # blocks per launch: one 128-column slab per CU over all phenotypes
+    batch = args.batch or max(1, min(gls_max_items() // len(hs), cus * 128 // (block * w.p_R * len(hs))))
+    res, outs = {}, {}
+    for prec in args.forms.split(","):
+        Bs = [torch.empty((m, 1, w.p), dtype=torch.float64, device="cuda") for _ in hs]
+        infos = [torch.empty((m,), dtype=torch.int32, device="cuda") for _ in hs]
+
+        def step(timing=False):
+            cs = [gls.Cohort(dM, precision=prec).whiten_fixed(dXL, dY, intercept_col=0)
+                  for dM, dY in zip(dMs, dYs)]
+            hs_all = [[c] + [c.fork(torch.cuda.current_stream()) for _ in range(batch - 1)]
+                      for c in cs]
+            for hh in hs_all:
+                for h in hh:
+                    h.reserve(block * w.p_R)
+            if timing:
+                hs_all[0][0].set_kernel_timing(True)
+            nblk = (m + block - 1) // block
+            for g0 in range(0, nblk, batch):
+                items = []
+                for j in range(len(hs)):
+                    for k, b in enumerate(range(g0, min(nblk, g0 + batch))):
+                        a, e = b * block, min(m, (b + 1) * block)
+                        items.append((hs_all[j][k], dXR[:, a * w.p_R:e * w.p_R], w.p_R, Bs[j][a:e],
+                                      infos[j][a:e]))
+                gls.solve_multi(items)
+            kt = hs_all[0][0].kernel_time(0) if timing else None
+            torch.cuda.synchronize()
+            for hh in hs_all:
+                for h in hh[1:]:
+                    h.free()
+            for c in cs:
+                c.free()
+            return kt
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        kts = [step(timing=True) for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        trsm_ms = sum(k[0] for k in kts)
+        trsm_n = sum(k[1] for k in kts)
+        flops = float(w.n) ** 2 * m * w.p_R * len(hs) * args.steps
+        peak = PEAK_FP64_TFLOPS if prec == "fp64" else PEAK_FP32_TFLOPS
+        res[prec] = {"value": round(len(hs) * m * args.steps / dt, 1), "unit": "b_ij/s",
+                     "ms_per_step": round(dt / args.steps * 1e3, 2),
+                     "trsm_tflops": round(flops / (trsm_ms * 1e-3) / 1e12, 3), "trsm_peak": peak,
+                     "trsm_launches": trsm_n, "blocks_per_launch_per_phenotype": batch,
+                     "rank_deficient": int(sum(int((inf != 0).sum()) for inf in infos))}
+        outs[prec] = [B.cpu().numpy() for B in Bs]
+        log(f"[{prec}] {res[prec]['value']:.0f} b_ij/s, {res[prec]['ms_per_step']:.1f} ms/step, "
+            f"TRSM {res[prec]['trsm_tflops']:.1f} TFLOP/s")
+    del dXR
+    if args.parity_sample > 0:
+        rng = np.random.default_rng(12107325)
+        idx = np.unique(np.concatenate([[0, m - 1], rng.choice(m, min(args.parity_sample, m) - 2,
+                                                              replace=False)]))
+        XRs = np.concatenate([dg.make_XR(w, int(i), 1) for i in idx], axis=1)
+        for j, M in enumerate(Ms):
+            ref = orc.gls_sequence(M, XL, XRs, Y[:, j:j + 1], w.p_R, lu=sla.lu_factor(M))
+            for prec in outs:
+                err = orc.relative_error(outs[prec][j][idx], ref)
+                key = "max_rel_err_by_phenotype"
+                res[prec].setdefault(key, []).append(float(err.max()))
+                log(f"[{prec}] phenotype {j} (h = {hs[j]}): max rel err {err.max():.3e} "
+                    f"on {len(idx)} problems")
+        for prec in outs:
+            res[prec]["parity_sample"] = int(len(idx))
+    forms = args.forms.split(",")
+    head = res[forms[0]]
+    out = {
+        "metric": "GLS solves/sec for t phenotypes with distinct M_j (n=1e4, p=4)",
+        "value": head["value"], "unit": "b_ij/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if forms[0] == "fp64" else "f32+f64", "data": "synthetic",
+        "config": {"workload": w.name, "n": w.n, "p": w.p, "p_L": w.p_L, "p_R": w.p_R,
+                   "phenotypes": len(hs), "h": list(hs), "m": m, "block": block,
+                   "M_j": f"h_j*ZZ^T/q+(1-h_j)I+1e-3I, q={w.q}", "parallelism": "1 GPU"},
+        "forms": res,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def gls_max_items():
+    """Work items the library puts in one launch of gls_solve_multi (more are
+    split over several launches)."""
+    return 16
+
+
 def serve_bench(args):
     """The serving mix: Poisson arrivals of GWAS jobs (n in {1500, 4000,
     10000, 20000}, p uniform in 4..20, m log-uniform in [1e5, m_max], each
@@ -613,6 +731,9 @@ def main():
         return
     if args.workload == "ablation" and args.gpus == 1:
         ablation_bench(args)
+        return
+    if args.workload == "phenotypes" and args.gpus == 1:
+        phenotypes_bench(args)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))

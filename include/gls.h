@@ -293,7 +293,12 @@ void gls_file_close(gls_file_source src);
  * solved by one more, on `stream` (not the handles' own streams; the
  * caller orders them).  Each item needs its own handle (or fork), because
  * the item uses the handle's workspace.  Results equal gls_solve_block's
- * for the same item bit for bit. */
+ * for the same item bit for bit.
+ * Phenotypes with distinct covariance matrices (the phenotype index of
+ * Eq. (1) with its own M_j, e.g. M_j = h_j Phi + (1 - h_j) I): factor each
+ * M_j into its own handle, whiten X_L and y_j on it, and pass one item per
+ * phenotype whose X_R points at the same genotype block; one launch then
+ * solves the block for every phenotype (X_R is only read). */
 typedef struct {
   gls_handle h;
   int64_t nsnp;

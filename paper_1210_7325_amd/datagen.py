@@ -223,7 +223,13 @@ SERVE_BASE = Workload("serving_mix", n=1500, p_L=3, p_R=1, t=1, m=100_000, block
                       q=3000, h=0.5, seed=MASTER_SEED + 3)
 STREAM = Workload("stream_n20000_p6_t8_m10M", n=20_000, p_L=5, p_R=1, t=8, m=10_000_000,
                   block=8192, q=40_000, h=0.5, seed=MASTER_SEED + 4)
-WORKLOADS = {w.name: w for w in (SMALL, SCALE, MIXED, SERVE_BASE, STREAM)}
+# Phenotypes with distinct covariance matrices (the phenotype index of Eq. (1)
+# with its own M_j): t = 4 phenotypes y_j, M_j = h_j Phi + (1 - h_j) I + 1e-3 I
+# with the heritabilities below, one shared X_R.
+PHENO = Workload("phenotypes_n10000_p4_t4_distinctM", n=10_000, p_L=3, p_R=1, t=4, m=131_072,
+                 block=4096, q=20_000, h=0.5, seed=MASTER_SEED + 5)
+PHENO_H = (0.2, 0.4, 0.6, 0.8)
+WORKLOADS = {w.name: w for w in (SMALL, SCALE, MIXED, SERVE_BASE, STREAM, PHENO)}
 
 
 def make_Z(w: Workload) -> np.ndarray:
