@@ -535,6 +535,8 @@ def ablation_bench(args):
             f"{dt / launches * 1e3:.2f} ms/launch")
         for h in hs[1:]:
             h.free()
+    c.set_slab_cols(0)
+    algs = algorithm_ablation(torch, gls, w, M, dM, dXL, dY, dXR, B, c)
     c.free()
     head = rows[-1]
     fixed = [r for r in rows if r["slab_cols"] == 64]
@@ -548,11 +550,103 @@ def ablation_bench(args):
         "grouping": rows,
         "grouping_gain_64_col_slabs": round(fixed[-1]["value"] / fixed[0]["value"], 1),
         "grouping_gain_auto_slabs": round(rows[-1]["value"] / rows[len(fixed)]["value"], 1),
-        "note": ("per-problem whitening of the whole X_i (the paper's seq-gls structure) would add "
-                 f"a factor p = {w.p} of trsm work; a per-problem trsv reads L (n^2/2 doubles) "
-                 "once per problem, at most 8 TB/s / 400 MB = 2e4 problems/s at n = 1e4"),
+        "algorithms": algs,
     }
     print(json.dumps(out), flush=True)
+
+
+def algorithm_ablation(torch, gls, w, M, dM, dXL, dY, dXR, Bhp, c):
+    """The paper's algorithms of Fig. 2 on the GPU, n = 10^4, p = 4, on the
+    library's own triangular-solve kernels (FP64 right-hand sides through
+    gls_whiten_block_f64 where the algorithm whitens whole X_i):
+
+      Alg. 3 (black-box): per problem, factor M, whiten X_i (p columns) and
+        y, then S_i = X_i^T X_i, b_i = X_i^T y, b_i = S_i^-1 b_i;
+      Alg. 4 (seq-gls): factor M and whiten y once; per problem whiten X_i
+        (p columns: few right-hand sides per launch), then as above;
+      Alg. 4 grouped: the same, with the p columns of 8,192 problems whitened
+        by one launch (32,768 right-hand sides, as a full launch of Alg. 5);
+      Alg. 5 (hp-gwas): the library's solve (fixed part once, only the
+        genotype column of each problem whitened), 32,768 problems per launch
+        (the last row of the grouping sweep).
+
+    The small products and p x p solves of Alg. 3 and Alg. 4 are batched
+    torch FP64 operations (bmm, linalg.solve): they are not the part being
+    compared.  Each variant's b_i are checked against Alg. 5's on the
+    problems it solved."""
+    p, n = w.p, w.n
+    yt = c.whiten_block(dY)                                   # L^{-1} y (trsv)
+    XR64 = dXR.double()
+
+    def design(i0, g):
+        """[X_L | x_i] for problems i0..i0+g-1, n x (p g) column-major FP64."""
+        X = torch.empty((g, p, n), dtype=torch.float64, device="cuda")
+        X[:, :w.p_L, :] = dXL.t().unsqueeze(0)
+        X[:, w.p_L:, :] = XR64[:, i0:i0 + g].t().unsqueeze(1)
+        return X.reshape(g * p, n).t()
+
+    def finish(W, g, ytil):
+        Wb = W.t().reshape(g, p, n)                            # W_i^T, (g, p, n)
+        S = torch.bmm(Wb, Wb.transpose(1, 2).contiguous())     # X_i^T M^-1 X_i
+        r = torch.matmul(Wb, ytil)                             # X_i^T M^-1 y
+        return torch.linalg.solve(S, r)[:, :, 0]
+
+    res = {}
+    # Alg. 4, one problem per launch
+    k4 = 32
+    out4 = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(k4):
+        out4.append(finish(c.whiten_block(design(i, 1)), 1, yt))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    res["alg4_seq_gls_per_problem"] = {"problems": k4, "ms_per_problem": round(dt / k4 * 1e3, 3),
+                                       "value": round(k4 / dt, 1)}
+    # Alg. 4 grouped: 8,192 problems (32,768 FP64 columns) per launch
+    g = 8192
+    Wg = torch.empty((g * p, n), dtype=torch.float64, device="cuda").t()
+    outg = finish(c.whiten_block(design(0, g), Wg), g, yt)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for rep in range(2):
+        outg = finish(c.whiten_block(design(rep * g, g), Wg), g, yt)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    res["alg4_seq_gls_grouped"] = {"problems_per_launch": g, "rhs_per_launch": g * p,
+                                   "ms_per_launch": round(dt / 2 * 1e3, 3),
+                                   "value": round(2 * g / dt, 1)}
+    del Wg
+    # Alg. 3, black-box: the factorization inside the loop
+    k3 = 6
+    out3 = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(k3):
+        ci = gls.Cohort(dM)
+        yti = ci.whiten_block(dY)
+        out3.append(finish(ci.whiten_block(design(i, 1)), 1, yti))
+        ci.free()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    res["alg3_black_box"] = {"problems": k3, "ms_per_problem": round(dt / k3 * 1e3, 3),
+                             "value": round(k3 / dt, 1)}
+    # Alg. 5 at the same grouping (32,768 right-hand sides per launch)
+    hb = Bhp[:, 0, :].double()
+    ref = hb[:g]                      # Alg. 5's b of the first problems (from the grouping sweep)
+    errs = {
+        "alg4_seq_gls_per_problem": float(((torch.cat(out4) - ref[:k4]).abs().amax(1)
+                                           / ref[:k4].abs().amax(1)).max()),
+        "alg4_seq_gls_grouped": float(((outg - hb[g:2 * g]).abs().amax(1)
+                                       / hb[g:2 * g].abs().amax(1)).max()),
+        "alg3_black_box": float(((torch.cat(out3) - ref[:k3]).abs().amax(1)
+                                 / ref[:k3].abs().amax(1)).max()),
+    }
+    for k, e in errs.items():
+        res[k]["max_rel_err_vs_alg5"] = e
+    for k, v in res.items():
+        log(f"[ablation] {k}: {v['value']:.1f} b_i/s ({v}), max rel err vs Alg. 5 {errs[k]:.2e}")
+    return res
 
 
 def phenotypes_bench(args):

@@ -190,6 +190,17 @@ int gls_copy_fixed(gls_handle h, double* WL, int64_t ldwl, double* Yt,
 int gls_whiten_block(gls_handle h, int64_t ncols, const int8_t* X, int64_t ldx,
                      double* W, int64_t ldw);
 
+/* W = L^{-1} X for FP64 X (n x ncols, ldx >= n) into the caller's n x ncols
+ * FP64 array (ldw >= n): the triangular solve of whole design matrices, as
+ * the per-problem trsm of Alg. 3 and Alg. 4 applies it to all p columns of
+ * X_i (and as the fixed part's X_L and y are whitened).  FP64 handles only
+ * (GLS_E_UNSUPPORTED for GLS_FP32_REFINE).  Same kernels as the genotype
+ * solve, with FP64 right-hand sides in 16-, 64- or 128-column slabs (a
+ * 32-column setting uses 64).  Asynchronous; grows the workspace like
+ * gls_solve_block. */
+int gls_whiten_block_f64(gls_handle h, int64_t ncols, const double* X, int64_t ldx, double* W,
+                         int64_t ldw);
+
 /* ---- tuning and measurement -------------------------------------------- */
 
 /* Columns of genotypes per work-group of the triangular-solve kernel: 16

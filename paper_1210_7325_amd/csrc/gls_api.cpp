@@ -637,6 +637,32 @@ int gls_whiten_block(gls_handle h, int64_t ncols, const int8_t* X, int64_t ldx, 
   return GLS_OK;
 }
 
+int gls_whiten_block_f64(gls_handle h, int64_t ncols, const double* X, int64_t ldx, double* W,
+                         int64_t ldw) {
+  if (!h) return -1;
+  if (ncols < 0) return -2;
+  if (ncols > 0 && !X) return -3;
+  if (ldx < h->c->n) return -4;
+  if (ncols > 0 && !W) return -5;
+  if (ldw < h->c->n) return -6;
+  if (h->c->info != 0) return GLS_E_STATE;
+  if (h->c->prec != GLS_FP64) return GLS_E_UNSUPPORTED;
+  if (ncols == 0) return GLS_OK;
+  int rc = ensure_workspace(h, ncols);
+  if (rc) return rc;
+  JobTable tab;
+  tab.njobs = 1;
+  tab.j[0] = make_job(h, own_workspace(h), 0, ncols, X, ldx);
+  const gls_work item{h, ncols, 1, nullptr, ldx, nullptr, 0, nullptr};
+  int C = slab_cols_for(&item, 1);
+  if (C == 32) C = 64;  // FP64 right-hand sides come in 16-, 64- and 128-column slabs
+  TimedScope t0(h, 0);
+  HIPCHK(launch_trsm_f64(tab, (ncols + C - 1) / C, C, h->stream));
+  t0.end();
+  HIPCHK(launch_slab_to_colmajor(h->W, C, h->c->n_pad, h->c->n, 0, ncols, W, ldw, h->stream));
+  return GLS_OK;
+}
+
 int gls_set_slab_cols(gls_handle h, int cols) {
   if (!h) return -1;
   if (cols != 0 && cols != 16 && cols != 32 && cols != 64 && cols != 128) return -2;

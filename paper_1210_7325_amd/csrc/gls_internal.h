@@ -90,6 +90,7 @@ hipError_t launch_factor(const double* M, int64_t ldm, int64_t n, int64_t n_pad,
 hipError_t launch_unpack_factor(const double* Lstrips, const double* Ldiag, int64_t n, double* L,
                                 int64_t ldl, hipStream_t st);
 hipError_t launch_trsm_i8(const JobTable& tab, int64_t nslabs, int C, hipStream_t st);
+hipError_t launch_trsm_f64(const JobTable& tab, int64_t nslabs, int C, hipStream_t st);
 hipError_t launch_slab_to_colmajor(const double* W, int C, int64_t n_pad, int64_t n, int64_t col0,
                                    int64_t ncols, double* out, int64_t ldo, hipStream_t st);
 hipError_t launch_fixed_solve(const double* XL, int64_t ldx, const double* Y, int64_t ldy,

@@ -315,7 +315,7 @@ __global__ __launch_bounds__(64 * WR * WC) void k_trsm(const JobTable tab) {
 // step W = inv(L_kk) R and the store run as in k_trsm (rows beyond the first
 // tile give W = 0, as padding must).  Without this, one wave row would do
 // the whole GEMM while the others multiply padding.
-template <int C, int WR, int WC, int D>
+template <int C, int WR, int WC, int D, typename TIn = int8_t>
 __global__ __launch_bounds__(64 * WR * WC) void k_trsm_last(const JobTable tab) {
   constexpr int RW = NB / WR, RT = RW / 16;
   constexpr int CW = C / WC, CT = CW / 16;
@@ -330,7 +330,7 @@ __global__ __launch_bounds__(64 * WR * WC) void k_trsm_last(const JobTable tab) 
   if (!last_block_split(J.n, K, RW)) return;
   const int k = K - 1;
   const int64_t slab = (int64_t)blockIdx.x - J.slab0;
-  const int8_t* __restrict__ X = reinterpret_cast<const int8_t*>(J.X);
+  const TIn* __restrict__ X = reinterpret_cast<const TIn*>(J.X);
   double* __restrict__ Wslab = J.W + slab * (int64_t)K * NB * C;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x % 64;
   const int wr = wave / WC, wc = wave % WC;
@@ -345,7 +345,7 @@ __global__ __launch_bounds__(64 * WR * WC) void k_trsm_last(const JobTable tab) 
     for (int ct = 0; ct < CT; ct++)
 #pragma unroll
       for (int i = 0; i < 4; i++)
-        xv[rt][ct][i] = load_x<int8_t>(X, J.ldx, (int64_t)k * NB + rt * 16 + lane / 16 + 4 * i,
+        xv[rt][ct][i] = load_x<TIn>(X, J.ldx, (int64_t)k * NB + rt * 16 + lane / 16 + 4 * i,
                                        col_base + ct * 16 + lane % 16, J.n, J.ncols);
   d4 acc[RT][CT];
 #pragma unroll
@@ -486,6 +486,30 @@ hipError_t launch_trsm_i8(const JobTable& tab, int64_t nslabs, int C, hipStream_
       // in registers only without the register ring
       k_trsm<128, 4, 2, TRSM_DEPTH, int8_t, 2, 4><<<(unsigned)nslabs, 512, 0, st>>>(tab);
       if (last) k_trsm_last<128, 4, 2, 2><<<(unsigned)nslabs, 512, 0, st>>>(tab);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// The same solve for FP64 right-hand sides (whole design matrices, as the
+// per-problem trsm of Alg. 3 and Alg. 4 whitens them): 16-, 64- and
+// 128-column slabs.
+hipError_t launch_trsm_f64(const JobTable& tab, int64_t nslabs, int C, hipStream_t st) {
+  bool last = false;
+  for (int i = 0; i < tab.njobs; i++) last = last || last_block_split(tab.j[i].n, tab.j[i].K, LAST_RW);
+  switch (C) {
+    case 16:
+      k_trsm<16, 8, 1, 8, double><<<(unsigned)nslabs, 512, 0, st>>>(tab);
+      if (last) k_trsm_last<16, 4, 1, TRSM_DEPTH, double><<<(unsigned)nslabs, 256, 0, st>>>(tab);
+      break;
+    case 64:
+      k_trsm<64, 4, 2, TRSM_DEPTH, double, 2, 4><<<(unsigned)nslabs, 512, 0, st>>>(tab);
+      if (last) k_trsm_last<64, 4, 2, TRSM_DEPTH, double><<<(unsigned)nslabs, 512, 0, st>>>(tab);
+      break;
+    case 128:
+      k_trsm<128, 4, 2, TRSM_DEPTH, double, 2, 4><<<(unsigned)nslabs, 512, 0, st>>>(tab);
+      if (last) k_trsm_last<128, 4, 2, 2, double><<<(unsigned)nslabs, 512, 0, st>>>(tab);
       break;
     default: return hipErrorInvalidValue;
   }

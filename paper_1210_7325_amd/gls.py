@@ -36,6 +36,7 @@ EXPORTS = ("gls_factor", "gls_whiten_fixed", "gls_solve_block", "gls_solve_block
            "gls_reserve", "gls_free",
            "gls_fork", "gls_set_stream", "gls_footprint_bytes", "gls_last_info",
            "gls_strerror", "gls_copy_factor", "gls_copy_fixed", "gls_whiten_block",
+           "gls_whiten_block_f64",
            "gls_solve_multi", "gls_set_slab_cols", "gls_set_kernel_timing", "gls_kernel_time",
            "gls_solve_stream", "gls_file_open", "gls_file_fill", "gls_file_stats",
            "gls_file_close")
@@ -89,6 +90,7 @@ def lib() -> ctypes.CDLL:
             "gls_copy_factor": (_int, [_p, _p, _i64]),
             "gls_copy_fixed": (_int, [_p, _p, _i64, _p, _i64, _p, _p]),
             "gls_whiten_block": (_int, [_p, _i64, _p, _i64, _p, _i64]),
+            "gls_whiten_block_f64": (_int, [_p, _i64, _p, _i64, _p, _i64]),
             "gls_solve_multi": (_int, [ctypes.POINTER(gls_work), _i64, _p]),
             "gls_set_slab_cols": (_int, [_p, _int]),
             "gls_set_kernel_timing": (_int, [_p, _int]),
@@ -183,6 +185,10 @@ def gls_copy_fixed(h, WL, ldwl, Yt, ldyt, S_TL, C_T) -> int:
 
 def gls_whiten_block(h, ncols, X, ldx, W, ldw) -> int:
     return lib().gls_whiten_block(h, ncols, X, ldx, W, ldw)
+
+
+def gls_whiten_block_f64(h, ncols, X, ldx, W, ldw) -> int:
+    return lib().gls_whiten_block_f64(h, ncols, X, ldx, W, ldw)
 
 
 def gls_solve_multi(items, stream) -> int:
@@ -328,13 +334,22 @@ class Cohort:
                              info.data_ptr()), "gls_solve_block")
         return B, info
 
-    def whiten_block(self, X):
+    def whiten_block(self, X, W=None):
+        """L^{-1} X for int8 (gls_whiten_block) or FP64 (gls_whiten_block_f64)
+        X of shape (n, ncols); returns W, or writes the caller's column-major W."""
         torch = _torch()
         with torch.cuda.stream(self.stream):
             X = colmajor(X)
-            W = torch.empty((X.shape[1], X.shape[0]), dtype=torch.float64, device=X.device).t()
-        _chk(gls_whiten_block(self.h, int(X.shape[1]), X.data_ptr(), _ld(X), W.data_ptr(),
-                              int(X.shape[0])), "gls_whiten_block")
+            if W is None:
+                W = torch.empty((X.shape[1], X.shape[0]), dtype=torch.float64, device=X.device).t()
+        assert W.dtype == torch.float64 and W.stride(0) == 1
+        if X.dtype == torch.float64:
+            _chk(gls_whiten_block_f64(self.h, int(X.shape[1]), X.data_ptr(), _ld(X), W.data_ptr(),
+                                      _ld(W)), "gls_whiten_block_f64")
+        else:
+            assert X.dtype == torch.int8
+            _chk(gls_whiten_block(self.h, int(X.shape[1]), X.data_ptr(), _ld(X), W.data_ptr(),
+                                  _ld(W)), "gls_whiten_block")
         return W
 
     def copy_factor(self):

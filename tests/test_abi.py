@@ -18,7 +18,7 @@ pytestmark = pytest.mark.skipif(not os.path.exists(gls.LIB_PATH), reason="libgls
 def declared_functions():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(gls_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(gls_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_exports_every_declared_symbol():
@@ -49,6 +49,7 @@ def test_argument_validation_without_device():
     assert L.gls_copy_factor(None, 1, 10) == -1
     assert L.gls_copy_fixed(None, None, 0, None, 0, None, None) == -1
     assert L.gls_whiten_block(None, 1, 1, 10, 1, 10) == -1
+    assert L.gls_whiten_block_f64(None, 1, 1, 10, 1, 10) == -1
     out = ctypes.c_void_p()
     assert L.gls_fork(None, None, ctypes.byref(out)) == -1
     assert L.gls_fork(None, None, None) == -3

@@ -83,6 +83,24 @@ def test_whiten_block_matches_oracle(G, n, ncols):
     c.free()
 
 
+@pytest.mark.parametrize("n,ncols,slab", [(1000, 200, 0), (129, 65, 16), (660, 300, 64),
+                                           (513, 130, 128), (1000, 4, 0), (700, 3000, 0)])
+def test_whiten_block_f64_matches_oracle(G, n, ncols, slab):
+    """FP64 right-hand sides (whole design matrices: covariates, phenotypes,
+    genotypes as doubles) through gls_whiten_block_f64, each slab width;
+    n = 660 leaves its last row block to the last-block kernel."""
+    say("whiten f64 n=", n, "ncols=", ncols, "slab", slab)
+    rng = np.random.default_rng(n + ncols)
+    w, M, XL, Y, XR = small_problem(n, m=4)
+    X = rng.standard_normal((n, ncols))
+    c = G.Cohort(to_dev(M))
+    c.set_slab_cols(slab)
+    W = c.whiten_block(to_dev(X)).cpu().numpy()
+    Wref = orc.whiten(orc.cholesky_lower(M), X)
+    assert maxrel(W, Wref) < TOL_MID
+    c.free()
+
+
 @pytest.mark.parametrize("pL,t", [(3, 1), (16, 1), (5, 8), (1, 2)])
 def test_fixed_part_matches_oracle(G, pL, t):
     say("fixed pL=", pL, "t=", t)
