@@ -75,6 +75,9 @@ def parse():
     ap.add_argument("--stream-source", choices=("generator", "file"), default="generator",
                     help="stream workload: genotypes from the host generator or from a file "
                          "read by the library's reader (written first, removed after)")
+    ap.add_argument("--stream-sink", choices=("memory", "file"), default="memory",
+                    help="stream workload: results to host memory, or to a file written by the "
+                         "library's asynchronous writer (removed after the run)")
     ap.add_argument("--stream-file", default=None,
                     help="genotype file for --stream-source file (default: under $TMPDIR)")
     ap.add_argument("--stream-direct", type=int, default=1,
@@ -362,12 +365,16 @@ def host_info():
 
 
 def stream_bench(args):
-    """The streamed form (Sec. 4, Alg. 8): genotypes produced on the host by
-    the C generator into pinned double buffers while the device solves, for
-    the n = 20,000, p = 6, t = 8 workload in blocks of 8192 problems.  Reports
-    the streamed rate, the device time inside the same run (so
-    overlap = device time / wall time) and the in-core rate of the same
-    problems with the genotypes resident."""
+    """The streamed form (Sec. 4, Alg. 8) for the n = 20,000, p = 6, t = 8
+    workload in blocks of 8192 problems: genotypes produced on the host (the
+    C generator, or the library's file reader with --stream-source file)
+    into pinned double buffers while the device solves; results handed to a
+    Python sink in host memory, or written to a file by the library's
+    asynchronous writer (--stream-sink file).  Reports the streamed rate,
+    the device time inside the same run (overlap = device time / wall
+    time), the paper's condition time(compute) against time(load) +
+    time(store), and the in-core rate of the first problems (at most 2^19)
+    with the genotypes resident, whose results must be the same bits."""
     import scipy.linalg as sla
     import torch
     from oracle import gls_oracle as orc
@@ -375,6 +382,7 @@ def stream_bench(args):
     w = dg.STREAM
     m = args.m or 64 * w.block
     block = args.block or w.block
+    m_in = min(m, 1 << 19)  # the in-core comparison's problems
     forms = args.forms.split(",")
     torch.cuda.set_device(0)
     t0 = time.time()
@@ -384,11 +392,11 @@ def stream_bench(args):
     dM = torch.from_numpy(M).cuda()
     dXL = torch.from_numpy(np.asfortranarray(XL)).cuda()
     dY = torch.from_numpy(np.asfortranarray(Y)).cuda()
+    import tempfile
+    tmpdir = args.stream_file and os.path.dirname(args.stream_file) or tempfile.gettempdir()
     src = None
     if args.stream_source == "file":
-        import tempfile
-        path = args.stream_file or os.path.join(tempfile.gettempdir(),
-                                                f"gls_genotypes_n{w.n}_m{m}.bin")
+        path = args.stream_file or os.path.join(tmpdir, f"gls_genotypes_n{w.n}_m{m}.bin")
         t0 = time.time()
         nbytes = stream.write_genotype_file(path, w, m)
         log(f"genotype file {path}: {nbytes / 1e9:.2f} GB written in {time.time() - t0:.1f}s")
@@ -396,6 +404,7 @@ def stream_bench(args):
         fill, ctx = src.fill, src.ctx
     else:
         fill, ctx = stream.workload_fill(w)
+    dXR = upload_genotypes(torch, w, m_in)
     res, outs = {}, {}
     for prec in forms:
         t0 = time.perf_counter()
@@ -407,24 +416,33 @@ def stream_bench(args):
         stream.solve_stream(c, 0, min(m, 2 * block), block, w.p_R, fill, ctx)  # warm-up
         c.set_kernel_timing(True)
         read0 = src.stats() if src else (0, 0.0)
-        B, info, st = stream.solve_stream(c, 0, m, block, w.p_R, fill, ctx)
+        wst = None
+        if args.stream_sink == "file":
+            bpath = os.path.join(tmpdir, f"gls_b_{prec}_m{m}.bin")
+            wr = stream.FileWriter(bpath, None, w.t, w.p, snp_base=0, depth=4)
+            try:
+                st = stream.solve_stream_to(c, 0, m, block, w.p_R, fill, ctx, wr.sink, wr.ctx)
+            finally:
+                wst = wr.close()
+            B = np.memmap(bpath, dtype=np.float64, mode="r", shape=(m, w.t, w.p))
+        else:
+            B, info, st = stream.solve_stream(c, 0, m, block, w.p_R, fill, ctx)
         read1 = src.stats() if src else (0, 0.0)
         dev_ms = c.kernel_time(0)[0] + c.kernel_time(1)[0]
         c.set_kernel_timing(False)
-        # in-core: the same problems with the genotypes resident, 4 blocks per launch
-        dXR = upload_genotypes(torch, w, m)
-        Bin = torch.empty((m, w.t, w.p), dtype=torch.float64, device="cuda")
-        inf = torch.empty((m,), dtype=torch.int32, device="cuda")
+        # in-core: the first m_in problems with the genotypes resident, 4 blocks per launch
+        Bin = torch.empty((m_in, w.t, w.p), dtype=torch.float64, device="cuda")
+        inf = torch.empty((m_in,), dtype=torch.int32, device="cuda")
         hs = [c] + [c.fork(torch.cuda.current_stream()) for _ in range(3)]
         for h in hs:
             h.reserve(block * w.p_R)
 
         def in_core():
-            nblk = (m + block - 1) // block
+            nblk = (m_in + block - 1) // block
             for g0 in range(0, nblk, 4):
                 items = []
                 for j, b in enumerate(range(g0, min(nblk, g0 + 4))):
-                    a, e = b * block, min(m, (b + 1) * block)
+                    a, e = b * block, min(m_in, (b + 1) * block)
                     items.append((hs[j], dXR[:, a * w.p_R:e * w.p_R], w.p_R, Bin[a:e], inf[a:e]))
                 gls.solve_multi(items)
             torch.cuda.synchronize()
@@ -432,31 +450,44 @@ def stream_bench(args):
         t1 = time.perf_counter()
         in_core()
         in_core_s = time.perf_counter() - t1
-        same = bool(np.array_equal(Bin.cpu().numpy(), B))
+        same = bool(np.array_equal(Bin.cpu().numpy(), np.asarray(B[:m_in])))
         for h in hs[1:]:
             h.free()
         c.free()
-        del dXR, Bin
+        del Bin
         wall_s = st["wall_ms"] * 1e-3
+        nblocks = st["blocks"]
+        store_ms = st["sink_ms"] + (wst["write_ms"] + wst["close_ms"] if wst else 0.0)
         res[prec] = {
             "value": round(m / wall_s, 1), "unit": "b_i/s", "wall_ms": round(st["wall_ms"], 1),
             "device_ms": round(dev_ms, 1), "overlap": round(dev_ms / st["wall_ms"], 4),
             "fill_ms": round(st["fill_ms"], 1), "sink_ms": round(st["sink_ms"], 1),
             "host_wait_ms": round(st["wait_ms"], 1),
             "h2d_gbps": round(st["bytes_h2d"] / wall_s / 1e9, 2),
-            "in_core_value": round(m / in_core_s, 1),
-            "streamed_vs_in_core": round(in_core_s / wall_s, 4),
+            "in_core_value": round(m_in / in_core_s, 1), "in_core_problems": m_in,
+            "streamed_vs_in_core": round((m_in / in_core_s) / (m / wall_s), 4),
             "bitwise_equal_to_in_core": same,
-            "per_block_device_ms": round(dev_ms / st["blocks"], 2),
-            "per_block_fill_ms": round(st["fill_ms"] / st["blocks"], 2),
+            "per_block_device_ms": round(dev_ms / nblocks, 2),
+            "per_block_fill_ms": round(st["fill_ms"] / nblocks, 2),
+            "per_block_store_ms": round(store_ms / nblocks, 2),
+            # Sec. 4: the I/O hides behind the computation when
+            # time(compute) > time(load) + time(store)
+            "compute_over_io": round(dev_ms / max(st["fill_ms"] + store_ms, 1e-9), 3),
             "factor_and_whiten_ms": round(setup_ms, 1),
         }
+        if wst:
+            res[prec].update({"b_file_bytes": wst["bytes"], "write_ms": round(wst["write_ms"], 1),
+                              "writer_wait_ms": round(wst["wait_ms"], 1),
+                              "close_ms": round(wst["close_ms"], 1),
+                              "write_gbps": round(wst["bytes"] / max(wst["write_ms"], 1e-9) / 1e6, 2)})
         if src:
             rb, rms = read1[0] - read0[0], read1[1] - read0[1]
             res[prec]["file_read_gbps"] = round(rb / max(rms, 1e-9) / 1e6, 2)
         outs[prec] = B
         log(f"[{prec}] streamed {m / wall_s:.0f} b_i/s (device {dev_ms:.0f} of {st['wall_ms']:.0f} ms, "
-            f"fill {st['fill_ms']:.0f} ms), in-core {m / in_core_s:.0f} b_i/s, bitwise equal {same}")
+            f"fill {st['fill_ms']:.0f} ms, store {store_ms:.0f} ms), in-core {m_in / in_core_s:.0f} "
+            f"b_i/s, bitwise equal {same}")
+    del dXR
     if src:
         src.close()
         os.remove(path)
@@ -464,6 +495,11 @@ def stream_bench(args):
     if args.parity_sample > 0:
         lu = sla.lu_factor(M)
         parity = parity_sample(w, m, M, XL, Y, lu, outs, min(args.parity_sample, 300))
+    if args.stream_sink == "file":
+        for prec in forms:
+            fname = outs[prec].filename
+            del outs[prec]
+            os.remove(fname)
     head = res[forms[0]]
     out = {
         "metric": "GLS solves/sec with streamed genotypes (n=2e4, p=6, t=8 phenotypes)",
@@ -476,6 +512,8 @@ def stream_bench(args):
                    "source": ("file read by gls_file_fill (written before the run, "
                               + ("O_DIRECT" if args.stream_direct else "buffered") + ")")
                    if src else "host C generator into pinned double buffers",
+                   "sink": ("file written by gls_writer_sink (asynchronous, depth 4, fdatasync at "
+                            "close)") if args.stream_sink == "file" else "host memory (Python sink)",
                    "parallelism": "1 GPU"},
         "forms": {k: {**v, **parity.get(k, {})} for k, v in res.items()},
     }

@@ -298,6 +298,37 @@ int gls_file_fill(void* source, int64_t snp0, int64_t nsnp, int8_t* buf, int64_t
 int gls_file_stats(gls_file_source src, int64_t* bytes, double* ms);
 void gls_file_close(gls_file_source src);
 
+/* ---- results to a file (disk-backed out-of-core, Sec. 4, Alg. 8) --------
+ * A ready-made sink callback for gls_solve_stream that writes b (and info)
+ * to files asynchronously, the output half of the paper's out-of-core
+ * algorithm: the write of a block's results overlaps the solve of the
+ * following blocks, and a buffer is reused only once its previous write
+ * has completed.  HOST code only (no device work, no HIP call).
+ * gls_writer_open(out, b_path, info_path, t, p, snp_base, depth) creates
+ *   (or overwrites in place) b_path, where problem s's (t, p) results go at
+ *   byte offset (s - snp_base) * t * p * 8 (FP64, phenotype-major within a
+ *   problem, the layout of gls_solve_block's B), and info_path (nullable),
+ *   where info[s] goes at (s - snp_base) * 4 (int32).  depth (1..64) is the
+ *   number of copied blocks that may wait to be written.  Returns 0, a
+ *   negative argument index, GLS_E_OOM or GLS_E_IO (cannot create a file).
+ * gls_writer_sink has the gls_sink_fn signature (pass the writer as
+ *   sink_ctx): it copies the block into a free buffer, waiting while all
+ *   depth buffers are still being written, queues the write and returns;
+ *   nonzero (which aborts the stream) after a failed write.  Blocks may
+ *   come in any order; each lands at its own offset.
+ * gls_writer_close drains the queue, flushes both files to the device
+ *   (fdatasync), closes them and releases the writer (NULL is a no-op); it
+ *   returns GLS_E_IO if any write or the flush failed.  The nullable
+ *   outputs receive the bytes written, the time in pwrite, the time sinks
+ *   waited for a free buffer and the time of the close itself, in ms.
+ * A writer may serve one stream at a time. */
+typedef struct gls_file_writer_s* gls_file_writer;
+int gls_writer_open(gls_file_writer* out, const char* b_path, const char* info_path, int64_t t,
+                    int64_t p, int64_t snp_base, int depth);
+int gls_writer_sink(void* writer, int64_t snp0, int64_t nsnp, const double* b, const int32_t* info);
+int gls_writer_close(gls_file_writer w, int64_t* bytes, double* write_ms, double* wait_ms,
+                     double* close_ms);
+
 /* ---- several cohorts in one launch (serving) ----------------------------
  * One work item per block of problems of one handle.  All items are
  * whitened by one launch of the triangular-solve kernel and assembled and

@@ -12,6 +12,14 @@
 // refuse direct I/O into them (the kernel cannot map their pages for the
 // transfer); the first such refusal switches the source to reading through
 // an aligned bounce buffer per thread (still O_DIRECT) and copying.
+//
+// Results to a file: a ready-made sink callback for gls_solve_stream (the
+// output half of Alg. 8: the asynchronous write of block j's b while later
+// blocks are computed, and the wait for the previous write before a buffer
+// is reused).  The sink copies the block into one of `depth` buffers and
+// returns; a writer thread writes the buffers in order with pwrite.  When
+// all buffers are waiting to be written, the sink blocks until the oldest
+// write completes.
 #include <fcntl.h>
 #include <unistd.h>
 
@@ -19,9 +27,12 @@
 #include <atomic>
 #include <cerrno>
 #include <chrono>
+#include <condition_variable>
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
+#include <mutex>
 #include <new>
 #include <thread>
 #include <vector>
@@ -93,7 +104,75 @@ int read_range(gls_file_source_s* s, int8_t* dst, int64_t off, int64_t len) {
   return err ? 1 : 0;
 }
 
+// pwrite the whole range; returns 0 or the errno of a failed call.
+int pwrite_all(int fd, const void* src, int64_t off, int64_t len) {
+  const char* p = static_cast<const char*>(src);
+  while (len > 0) {
+    const int64_t chunk = std::min<int64_t>(len, int64_t(1) << 30);
+    const ssize_t r = pwrite(fd, p, (size_t)chunk, (off_t)off);
+    if (r < 0 && errno == EINTR) continue;
+    if (r <= 0) return errno ? errno : EIO;
+    p += r;
+    off += r;
+    len -= r;
+  }
+  return 0;
+}
+
+struct WriteJob {
+  int64_t snp0 = 0, nsnp = 0;
+  std::vector<double> b;
+  std::vector<int32_t> info;
+};
+
 }  // namespace
+
+struct gls_file_writer_s {
+  int fd_b = -1, fd_info = -1;
+  int64_t t = 0, p = 0, base = 0;
+  int depth = 2;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<WriteJob> pending;  // copied blocks waiting to be written, in order
+  std::vector<WriteJob> spare;   // buffers free for reuse
+  int inflight = 0;              // jobs taken by the writer thread, not yet done
+  bool stop = false;
+  int err = 0;                   // first write error (errno)
+  std::thread th;
+  std::atomic<int64_t> bytes{0};
+  std::atomic<int64_t> write_ns{0};
+  std::atomic<int64_t> wait_ns{0};
+  std::atomic<int64_t> close_ns{0};
+
+  void run() {
+    std::unique_lock<std::mutex> lk(mu);
+    for (;;) {
+      cv.wait(lk, [&] { return stop || !pending.empty(); });
+      if (pending.empty()) return;  // stop requested and nothing left
+      WriteJob j = std::move(pending.front());
+      pending.pop_front();
+      inflight++;
+      lk.unlock();
+      const auto t0 = std::chrono::steady_clock::now();
+      int e = 0;
+      if (!err) {
+        const int64_t row = t * p * (int64_t)sizeof(double);
+        e = pwrite_all(fd_b, j.b.data(), (j.snp0 - base) * row, j.nsnp * row);
+        if (!e && fd_info >= 0)
+          e = pwrite_all(fd_info, j.info.data(), (j.snp0 - base) * (int64_t)sizeof(int32_t),
+                         j.nsnp * (int64_t)sizeof(int32_t));
+      }
+      write_ns += std::chrono::duration_cast<std::chrono::nanoseconds>(
+                      std::chrono::steady_clock::now() - t0).count();
+      if (!e) bytes += j.nsnp * (t * p * (int64_t)sizeof(double) + (fd_info >= 0 ? 4 : 0));
+      lk.lock();
+      if (e && !err) err = e;
+      spare.push_back(std::move(j));
+      inflight--;
+      cv.notify_all();
+    }
+  }
+};
 
 extern "C" {
 
@@ -170,6 +249,99 @@ void gls_file_close(gls_file_source src) {
   if (src->fd_direct >= 0) close(src->fd_direct);
   if (src->fd >= 0) close(src->fd);
   delete src;
+}
+
+int gls_writer_open(gls_file_writer* out, const char* b_path, const char* info_path, int64_t t,
+                    int64_t p, int64_t snp_base, int depth) {
+  if (!out) return -1;
+  *out = nullptr;
+  if (!b_path) return -2;
+  if (t < 1) return -4;
+  if (p < 1) return -5;
+  if (snp_base < 0) return -6;
+  if (depth < 1 || depth > 64) return -7;
+  gls_file_writer_s* w = new (std::nothrow) gls_file_writer_s;
+  if (!w) return GLS_E_OOM;
+  w->fd_b = open(b_path, O_WRONLY | O_CREAT | O_CLOEXEC, 0644);
+  if (w->fd_b >= 0 && info_path) w->fd_info = open(info_path, O_WRONLY | O_CREAT | O_CLOEXEC, 0644);
+  if (w->fd_b < 0 || (info_path && w->fd_info < 0)) {
+    if (w->fd_b >= 0) close(w->fd_b);
+    delete w;
+    return GLS_E_IO;
+  }
+  w->t = t;
+  w->p = p;
+  w->base = snp_base;
+  w->depth = depth;
+  try {
+    w->th = std::thread([w] { w->run(); });
+  } catch (...) {
+    close(w->fd_b);
+    if (w->fd_info >= 0) close(w->fd_info);
+    delete w;
+    return GLS_E_OOM;
+  }
+  *out = w;
+  return GLS_OK;
+}
+
+int gls_writer_sink(void* writer, int64_t snp0, int64_t nsnp, const double* b, const int32_t* info) {
+  gls_file_writer_s* w = static_cast<gls_file_writer_s*>(writer);
+  if (!w || snp0 < w->base || nsnp < 0 || (nsnp > 0 && !b)) return 1;
+  if (nsnp == 0) return 0;
+  std::unique_lock<std::mutex> lk(w->mu);
+  const auto t0 = std::chrono::steady_clock::now();
+  // wait(previous): a buffer is free once its write has completed
+  w->cv.wait(lk, [&] { return w->err || (int)w->pending.size() + w->inflight < w->depth; });
+  w->wait_ns += std::chrono::duration_cast<std::chrono::nanoseconds>(
+                    std::chrono::steady_clock::now() - t0).count();
+  if (w->err) return 1;
+  WriteJob j;
+  if (!w->spare.empty()) {
+    j = std::move(w->spare.back());
+    w->spare.pop_back();
+  }
+  lk.unlock();
+  try {
+    j.b.assign(b, b + nsnp * w->t * w->p);
+    if (info)
+      j.info.assign(info, info + nsnp);
+    else
+      j.info.assign((size_t)nsnp, 0);
+  } catch (...) {
+    return 1;
+  }
+  j.snp0 = snp0;
+  j.nsnp = nsnp;
+  lk.lock();
+  w->pending.push_back(std::move(j));  // async_write(b of this block)
+  w->cv.notify_all();
+  return 0;
+}
+
+int gls_writer_close(gls_file_writer w, int64_t* bytes, double* write_ms, double* wait_ms,
+                     double* close_ms) {
+  if (!w) return GLS_OK;
+  const auto t0 = std::chrono::steady_clock::now();
+  {
+    std::lock_guard<std::mutex> lk(w->mu);
+    w->stop = true;
+  }
+  w->cv.notify_all();
+  w->th.join();
+  int rc = w->err ? GLS_E_IO : GLS_OK;
+  if (fdatasync(w->fd_b) != 0 && rc == GLS_OK) rc = GLS_E_IO;
+  if (w->fd_info >= 0 && fdatasync(w->fd_info) != 0 && rc == GLS_OK) rc = GLS_E_IO;
+  close(w->fd_b);
+  if (w->fd_info >= 0) close(w->fd_info);
+  w->close_ns += std::chrono::duration_cast<std::chrono::nanoseconds>(
+                     std::chrono::steady_clock::now() - t0).count();
+  if (bytes) *bytes = w->bytes.load();
+  if (write_ms) *write_ms = (double)w->write_ns.load() * 1e-6;
+  if (wait_ms) *wait_ms = (double)w->wait_ns.load() * 1e-6;
+  if (close_ms) *close_ms = (double)w->close_ns.load() * 1e-6;
+  delete w;
+  return rc;
 }
 
 }  // extern "C"

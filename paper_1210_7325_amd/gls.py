@@ -39,7 +39,7 @@ EXPORTS = ("gls_factor", "gls_whiten_fixed", "gls_solve_block", "gls_solve_block
            "gls_whiten_block_f64",
            "gls_solve_multi", "gls_set_slab_cols", "gls_set_kernel_timing", "gls_kernel_time",
            "gls_solve_stream", "gls_file_open", "gls_file_fill", "gls_file_stats",
-           "gls_file_close")
+           "gls_file_close", "gls_writer_open", "gls_writer_sink", "gls_writer_close")
 
 _i64, _p, _int = ctypes.c_int64, ctypes.c_void_p, ctypes.c_int
 
@@ -103,6 +103,12 @@ def lib() -> ctypes.CDLL:
             "gls_file_fill": (_int, [_p, _i64, _i64, _p, _i64]),
             "gls_file_stats": (_int, [_p, ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double)]),
             "gls_file_close": (None, [_p]),
+            "gls_writer_open": (_int, [ctypes.POINTER(_p), ctypes.c_char_p, ctypes.c_char_p, _i64,
+                                       _i64, _i64, _int]),
+            "gls_writer_sink": (_int, [_p, _i64, _i64, _p, _p]),
+            "gls_writer_close": (_int, [_p, ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_double)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -241,6 +247,26 @@ def gls_file_stats(src) -> Tuple[int, int, float]:
 
 def gls_file_close(src) -> None:
     lib().gls_file_close(src)
+
+
+def gls_writer_open(b_path: str, info_path: Optional[str], t: int, p: int, snp_base: int = 0,
+                    depth: int = 4) -> Tuple[int, int]:
+    h = _p()
+    rc = lib().gls_writer_open(ctypes.byref(h), os.fsencode(b_path),
+                               os.fsencode(info_path) if info_path else None, t, p, snp_base, depth)
+    return rc, h.value
+
+
+def gls_writer_sink(w, snp0, nsnp, b, info) -> int:
+    return lib().gls_writer_sink(w, snp0, nsnp, b, info)
+
+
+def gls_writer_close(w) -> Tuple[int, int, float, float, float]:
+    """Returns (return code, bytes written, ms in pwrite, ms sinks waited, ms of the close)."""
+    b, wr, wa, cl = _i64(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    rc = lib().gls_writer_close(w, ctypes.byref(b), ctypes.byref(wr), ctypes.byref(wa),
+                                ctypes.byref(cl))
+    return rc, b.value, wr.value, wa.value, cl.value
 
 
 def _torch():

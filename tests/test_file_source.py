@@ -69,3 +69,52 @@ def test_offset_and_errors(lib, tmp_path):
     assert gls.gls_file_open(path, n, 1, offset=-1)[0] == -5
     assert gls.gls_file_open(path, n, 1, threads=0)[0] == -7
     gls.gls_file_close(None)                        # no-op
+
+
+# --- the asynchronous writer of results (gls_writer_*) ---------------------------
+def _block(rng, nsnp, t, p):
+    return rng.standard_normal((nsnp, t, p)), rng.integers(-3, 5, nsnp).astype(np.int32)
+
+
+@pytest.mark.parametrize("t,p,depth", [(1, 4, 1), (8, 6, 2), (3, 20, 5)])
+def test_writer_round_trip(lib, tmp_path, t, p, depth):
+    """Blocks handed to the sink (in and out of order, more blocks than
+    buffers) land at their own offsets of the b and info files, bit for bit."""
+    rng = np.random.default_rng(t * 100 + p)
+    base, m = 1000, 900
+    bpath, ipath = str(tmp_path / "b.bin"), str(tmp_path / "info.bin")
+    B = np.zeros((m, t, p))
+    info = np.zeros(m, np.int32)
+    cuts = [0, 7, 300, 301, 555, 900]
+    order = [2, 0, 4, 1, 3]
+    rc, w = gls.gls_writer_open(bpath, ipath, t, p, base, depth)
+    assert rc == 0
+    for k in order:
+        a, e = cuts[k], cuts[k + 1]
+        b, inf = _block(rng, e - a, t, p)
+        B[a:e], info[a:e] = b, inf
+        b = np.ascontiguousarray(b)
+        assert gls.gls_writer_sink(w, base + a, e - a, b.ctypes.data, inf.ctypes.data) == 0
+    rc, nbytes, wr, wa, cl = gls.gls_writer_close(w)
+    assert rc == 0 and nbytes == m * (t * p * 8 + 4)
+    got = np.fromfile(bpath, dtype=np.float64).reshape(m, t, p)
+    assert np.array_equal(got, B)
+    assert np.array_equal(np.fromfile(ipath, dtype=np.int32), info)
+
+
+def test_writer_errors(lib, tmp_path):
+    rc, w = gls.gls_writer_open(str(tmp_path / "no" / "such" / "dir" / "b.bin"), None, 1, 4, 0, 2)
+    assert rc == gls.GLS_E_IO and not w
+    assert gls.gls_writer_open(str(tmp_path / "b.bin"), None, 0, 4, 0, 2)[0] == -4
+    assert gls.gls_writer_open(str(tmp_path / "b.bin"), None, 1, 4, 0, 0)[0] == -7
+    # a block before the base problem is refused without writing
+    rc, w = gls.gls_writer_open(str(tmp_path / "b.bin"), None, 1, 4, 10, 2)
+    b = np.zeros((3, 1, 4))
+    assert gls.gls_writer_sink(w, 9, 3, b.ctypes.data, None) != 0
+    assert gls.gls_writer_close(w)[0] == 0
+    # a device that refuses writes: the failure reaches the sink and the close
+    if os.path.exists("/dev/full"):
+        rc, w = gls.gls_writer_open("/dev/full", None, 1, 4, 0, 1)
+        if rc == 0:
+            gls.gls_writer_sink(w, 0, 3, b.ctypes.data, None)
+            assert gls.gls_writer_close(w)[0] == gls.GLS_E_IO

@@ -128,3 +128,33 @@ def test_stream_from_file_equals_generator(mods, tmp_path, direct):
             stream.solve_stream(c, 0, W.m, W.block, W.p_R, src.fill, src.ctx)
         assert e.value.code == 7                       # GLS_E_ABORTED: the fill failed
     c.free()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_refine"])
+def test_stream_file_to_file(mods, tmp_path, prec):
+    """The whole out-of-core loop of Alg. 8 through the library: genotypes
+    read from a file by gls_file_fill, results written to files by the
+    asynchronous writer (gls_writer_sink); the files hold the in-core
+    results bit for bit, within the oracle's tolerance."""
+    gls, stream = mods
+    say("stream file to file", prec)
+    c, M, XL, Y = cohort(gls, W, prec)
+    gpath = str(tmp_path / "genotypes.bin")
+    stream.write_genotype_file(gpath, W, W.m)
+    bpath, ipath = str(tmp_path / "b.bin"), str(tmp_path / "info.bin")
+    with stream.FileSource(gpath, W.n, W.p_R, direct=True, threads=4) as src:
+        wr = stream.FileWriter(bpath, ipath, W.t, W.p, snp_base=0, depth=2)
+        try:
+            st = stream.solve_stream_to(c, 0, W.m, W.block, W.p_R, src.fill, src.ctx, wr.sink, wr.ctx)
+        finally:
+            wst = wr.close()
+    assert st["blocks"] == (W.m + W.block - 1) // W.block
+    assert wst["bytes"] == W.m * (W.t * W.p * 8 + 4)
+    B = np.fromfile(bpath, dtype=np.float64).reshape(W.m, W.t, W.p)
+    info = np.fromfile(ipath, dtype=np.int32)
+    Bin, info_in = c.solve_block(to_dev(dg.make_XR(W, 0, W.m)), p_R=W.p_R)
+    torch.cuda.synchronize()
+    assert np.array_equal(B, Bin.cpu().numpy()) and np.all(info == 0)
+    ref = orc.gls_sequence(M, XL, dg.make_XR(W, 0, W.m), Y, W.p_R)
+    assert orc.relative_error(B, ref).max() < (1e-10 if prec == "fp64" else 1e-8)
+    c.free()
