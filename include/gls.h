@@ -335,7 +335,10 @@ int gls_writer_close(gls_file_writer w, int64_t* bytes, double* write_ms, double
  * solved by one more, on `stream` (not the handles' own streams; the
  * caller orders them).  Each item needs its own handle (or fork), because
  * the item uses the handle's workspace.  Results equal gls_solve_block's
- * for the same item bit for bit.
+ * for the same item bit for bit.  The library records, per handle, the
+ * stream of the last launch that used its workspace; growing the workspace
+ * (a later, larger block) and gls_free wait for that launch as well as for
+ * the handle's own stream.
  * Phenotypes with distinct covariance matrices (the phenotype index of
  * Eq. (1) with its own M_j, e.g. M_j = h_j Phi + (1 - h_j) I): factor each
  * M_j into its own handle, whiten X_L and y_j on it, and pass one item per

@@ -35,6 +35,7 @@ struct Cohort {
   double* STL = nullptr;       // pL x pL
   double* CT = nullptr;        // pL x t
   double* Z = nullptr;         // FP32_REFINE: row-major n_pad x (pL+t), M^{-1}[X_L | Y]
+  double* z1 = nullptr;        // FP32_REFINE: column sums of Z (pL+t)
   int cus = 256;               // compute units of the device the cohort lives on
   int device = 0;              // the device current at gls_factor
 };
@@ -55,6 +56,7 @@ struct gls_handle_s {
   float* W32 = nullptr;        // FP32_REFINE: FP32 copy of W (quad layout)
   double* shift = nullptr;     // FP32_REFINE: per-column centering shift
   double* XZ = nullptr;        // FP32_REFINE: per column (x - s)^T Z, MAXP + MAXT wide
+  hipEvent_t ws_used = nullptr;  // recorded on the stream of every launch that used the workspace
   bool timing = false;         // bracket kernel launches with events
   std::vector<TimedLaunch> timed;
   size_t ntimed = 0;
@@ -101,6 +103,7 @@ void cohort_free(Cohort* c) {
   dfree(c->STL);
   dfree(c->CT);
   dfree(c->Z);
+  dfree(c->z1);
   delete c;
 }
 
@@ -108,10 +111,25 @@ int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
 size_t strips_count(int K) { return (size_t)K * (size_t)(K - 1) / 2 * (size_t)NB * NB; }
 
+// Wait until no launch still uses h's workspace: the last launch that used
+// it may have gone to another stream than the handle's (gls_solve_multi).
+int workspace_idle(gls_handle h) {
+  if (h->ws_used) HIPCHK(hipEventSynchronize(h->ws_used));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return GLS_OK;
+}
+
+// Record that work just enqueued on st uses h's workspace.
+int workspace_used(gls_handle h, hipStream_t st) {
+  if (!h->ws_used) HIPCHK(hipEventCreateWithFlags(&h->ws_used, hipEventDisableTiming));
+  HIPCHK(hipEventRecord(h->ws_used, st));
+  return GLS_OK;
+}
+
 int ensure_workspace(gls_handle h, int64_t ncols) {
   const int64_t need = round_up(std::max<int64_t>(ncols, 1), MAX_C);
   if (need <= h->Wcols) return GLS_OK;
-  HIPCHK(hipStreamSynchronize(h->stream));
+  if (int rc = workspace_idle(h)) return rc;
   dfree(h->W);
   dfree(h->W32);
   dfree(h->shift);
@@ -159,6 +177,7 @@ XzDesc make_xz(gls_handle h, const Workspace& ws, int64_t grp0, int64_t ncols, c
   x.X = X;
   x.ldx = ldx;
   x.Z = h->c->Z;
+  x.z1 = h->c->z1;
   x.shift = ws.shift;
   x.XZ = ws.XZ;
   x.ldf = (int)(h->c->pL + h->c->t);
@@ -314,6 +333,11 @@ int launch_items(const gls_work* items, int64_t count, hipStream_t st, gls_handl
     e = launch_assemble_solve(at, groups, refine, st);
   }
   if (th) th->stream = keep;
+  if (e == hipSuccess && !ws) {
+    for (int64_t i = 0; i < count; i++)
+      if (items[i].nsnp > 0)
+        if (int rc = workspace_used(items[i].h, st)) return rc;
+  }
   return hip_code(e);
 }
 
@@ -394,7 +418,7 @@ size_t gls_footprint_bytes(int64_t n, int64_t p_L, int64_t p_R, int64_t t, int64
   b += n_pad * (size_t)round_up(std::max<int64_t>(max_cols, 1), MAX_C) * 8;  // workspace
   if (prec == GLS_FP32_REFINE) {
     b += strips_count(K) * 4;                                   // FP32 strips
-    b += n_pad * w * 8;                                         // Z
+    b += n_pad * w * 8 + (w + MAXP + MAXT) * 8;                 // Z, its padding, its column sums
     const size_t cols = (size_t)round_up(std::max<int64_t>(max_cols, 1), MAX_C);
     b += n_pad * cols * 4 + cols * 8 + cols * (MAXP + MAXT) * 8;  // W32, shift, XZ
   }
@@ -492,19 +516,26 @@ int gls_whiten_fixed(gls_handle h, int64_t p_L, const double* X_L, int64_t ldx, 
   dfree(c->STL);
   dfree(c->CT);
   dfree(c->Z);
+  dfree(c->z1);
   c->fixed = false;
   const int64_t w = p_L + t;
   int rc;
   if ((rc = dalloc(&c->F, (size_t)c->n_pad * w))) return rc;
   if ((rc = dalloc(&c->STL, (size_t)p_L * p_L))) return rc;
   if ((rc = dalloc(&c->CT, (size_t)p_L * t))) return rc;
-  if (c->prec == GLS_FP32_REFINE && (rc = dalloc(&c->Z, (size_t)c->n_pad * w))) return rc;
+  // Z carries MAXP + MAXT doubles of zeros past its last row: the centering
+  // pre-pass reads a fixed number of entries from every row
+  if (c->prec == GLS_FP32_REFINE && (rc = dalloc(&c->Z, (size_t)c->n_pad * w + MAXP + MAXT))) return rc;
+  if (c->prec == GLS_FP32_REFINE && (rc = dalloc(&c->z1, (size_t)w))) return rc;
+  if (c->prec == GLS_FP32_REFINE)
+    HIPCHK(hipMemsetAsync(c->Z + (size_t)c->n_pad * w, 0, sizeof(double) * (MAXP + MAXT), h->stream));
   c->pL = p_L;
   c->t = t;
   c->icol = intercept_col;
   HIPCHK(launch_fixed_solve(X_L, ldx, Y, ldy, c->n, c->n_pad, c->K, (int)p_L, (int)t, c->Lstrips,
                             c->LinvP, c->F, c->Z, h->stream));
   HIPCHK(launch_gram(c->F, c->n, (int)p_L, (int)t, c->STL, c->CT, h->stream));
+  if (c->prec == GLS_FP32_REFINE) HIPCHK(launch_colsum(c->Z, c->n, (int)w, c->z1, h->stream));
   c->fixed = true;
   return GLS_OK;
 }
@@ -566,7 +597,8 @@ int gls_fork(gls_handle h, void* stream, gls_handle* out) {
 
 void gls_free(gls_handle h) {
   if (!h) return;
-  (void)hipStreamSynchronize(h->stream);
+  (void)workspace_idle(h);
+  if (h->ws_used) (void)hipEventDestroy(h->ws_used);
   dfree(h->W);
   dfree(h->W32);
   dfree(h->shift);
@@ -634,7 +666,7 @@ int gls_whiten_block(gls_handle h, int64_t ncols, const int8_t* X, int64_t ldx, 
   }
   t0.end();
   HIPCHK(launch_slab_to_colmajor(h->W, C, h->c->n_pad, h->c->n, 0, ncols, W, ldw, h->stream));
-  return GLS_OK;
+  return workspace_used(h, h->stream);
 }
 
 int gls_whiten_block_f64(gls_handle h, int64_t ncols, const double* X, int64_t ldx, double* W,
@@ -660,7 +692,7 @@ int gls_whiten_block_f64(gls_handle h, int64_t ncols, const double* X, int64_t l
   HIPCHK(launch_trsm_f64(tab, (ncols + C - 1) / C, C, h->stream));
   t0.end();
   HIPCHK(launch_slab_to_colmajor(h->W, C, h->c->n_pad, h->c->n, 0, ncols, W, ldw, h->stream));
-  return GLS_OK;
+  return workspace_used(h, h->stream);
 }
 
 int gls_set_slab_cols(gls_handle h, int cols) {

@@ -317,98 +317,123 @@ __global__ __launch_bounds__(64 * AS_WAVES) void k_assemble_solve(const AsmTable
 
 // Centering pre-pass: per genotype column the exact dyadic shift
 // s = round(256 * mean(x)) / 256 (x - s is exact in FP32: at most 10
-// significant bits) and (x - s)^T Z with Z = M^{-1}[X_L | Y].
-// One work-group per 64 columns.  First pass: lane c sums column c over the
-// row octets w, w + 8, ... of its wave (one 8-byte load when the column
-// start and the leading dimension allow it, byte loads otherwise and in the
-// tail).  Second pass: (x - s)^T Z as the assembly's products on FP64 MFMA,
-// the A operand built from two genotype bytes per lane and tile (taken from
-// one 8-byte load of the octet under the same conditions as the first pass).
-__device__ __forceinline__ void xz_octet(const int8_t* __restrict__ x, int64_t o, int64_t n,
-                                         bool vec, int8_t (&b)[8]) {
-  const int64_t r0 = 8 * o;
-  if (vec && r0 + 8 <= n) {
-    const int2 v = *reinterpret_cast<const int2*>(x + r0);
-    __builtin_memcpy(b, &v, 8);
-  } else {
-#pragma unroll
-    for (int i = 0; i < 8; i++) b[i] = r0 + i < n ? x[r0 + i] : (int8_t)0;
-  }
-}
+// significant bits) and (x - s)^T Z with Z = M^{-1}[X_L | Y], in one read of
+// the genotypes: x^T Z and the integer column sum are accumulated together,
+// and (x - s)^T Z = x^T Z - s (1^T Z) with 1^T Z summed once per cohort.
+// One work-group per 64 columns, one column per lane; its XZ_WAVES waves
+// take contiguous segments of rows (multiples of 16), each lane reading 16
+// genotypes of its column per step (one 16-byte load when the column start
+// and the leading dimension allow it, byte loads otherwise and at the end of
+// a segment) and updating its ldf products with FP64 FMAs, the row of Z
+// being the same for the whole wave (scalar loads).  The segments' partial
+// products meet in LDS and are summed in wave order, so a column's result
+// depends on its column alone.  FMAs rather than matrix cores: there are
+// only ldf = p_L + t products per genotype, fewer than the 16-wide tile of
+// an FP64 MFMA.
+constexpr int XZ_WAVES = 8;
 
-template <int ET>
-__global__ __launch_bounds__(64 * AS_WAVES) void k_xz_shift(const XzTable tab) {
-  __shared__ int isum[AS_WAVES][AS_COLS];
-  __shared__ double sh[AS_COLS];
-  __shared__ double red[AS_WAVES][AS_COLS][17];
-  __shared__ double dots[AS_COLS][AS_DOTS];
+template <int LDFMAX>
+__global__ __launch_bounds__(64 * XZ_WAVES) void k_xz_shift(const XzTable tab) {
+  __shared__ double part[XZ_WAVES][4][64];
+  __shared__ int isum[XZ_WAVES][64];
   int jb = 0;
   while (jb + 1 < tab.njobs && (int64_t)blockIdx.x >= tab.j[jb + 1].grp0) jb++;
   const XzDesc& J = tab.j[jb];
-  const int64_t col0 = ((int64_t)blockIdx.x - J.grp0) * AS_COLS;
+  const int64_t col0 = ((int64_t)blockIdx.x - J.grp0) * 64;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
   const int lane = threadIdx.x % 64;
-  const int64_t n = J.n, noct = (n + 7) / 8;
-  {
-    const bool valid = col0 + lane < J.ncols;
-    const int8_t* __restrict__ x = J.X + (valid ? col0 + lane : col0) * J.ldx;
-    const bool vec = (reinterpret_cast<uintptr_t>(J.X) % 8 == 0) && (J.ldx % 8 == 0);
-    int s = 0;
-    for (int64_t o0 = wave; o0 < noct; o0 += 8 * 4) {
-      int8_t b[4][8];
-#pragma unroll
-      for (int st = 0; st < 4; st++)
-        xz_octet(x, o0 + 8 * st < noct ? o0 + 8 * st : noct, n, vec, b[st]);
-#pragma unroll
-      for (int st = 0; st < 4; st++)
-#pragma unroll
-        for (int i = 0; i < 8; i++) s += b[st][i];
-    }
-    isum[wave][lane] = s;
-  }
-  __syncthreads();
-  if (threadIdx.x < AS_COLS) {
-    int tot = 0;
-    for (int w = 0; w < AS_WAVES; w++) tot += isum[w][threadIdx.x];
-    const double shift = rint(256.0 * (double)tot / (double)n) / 256.0;
-    sh[threadIdx.x] = shift;
-    if (col0 + threadIdx.x < J.ncols) J.shift[col0 + threadIdx.x] = shift;
-  }
-  __syncthreads();
-  const int r = lane / 16, cl = lane % 16;
-  const int8_t* xs[4];
-  double sft[4];
-#pragma unroll
-  for (int ct = 0; ct < 4; ct++) {
-    const int64_t c = col0 + 16 * ct + cl;
-    xs[ct] = J.X + (c < J.ncols ? c : col0) * J.ldx;
-    sft[ct] = sh[16 * ct + cl];
-  }
-  // the lane's two genotypes of an octet (rows 8o + r and 8o + r + 4 of its
-  // column): one 8-byte load of the whole octet (shared by the column's four
-  // lanes) when aligned and inside the column, else two byte loads
-  const bool vec = (reinterpret_cast<uintptr_t>(J.X) % 8 == 0) && (J.ldx % 8 == 0);
-  auto loadA = [&](int ct, int64_t o) __attribute__((always_inline)) -> d2 {
-    if (vec && 8 * o + 8 <= n) {
-      const int2 v = *reinterpret_cast<const int2*>(xs[ct] + 8 * o);
-      const double a0 = (double)(int8_t)((v.x >> (8 * r)) & 0xff) - sft[ct];
-      const double a1 = (double)(int8_t)((v.y >> (8 * r)) & 0xff) - sft[ct];
-      return d2{a0, a1};
-    }
-    const int64_t r0 = 8 * o + r, r1 = r0 + 4;
-    const double a0 = r0 < n ? (double)xs[ct][r0] - sft[ct] : 0.0;
-    const double a1 = r1 < n ? (double)xs[ct][r1] - sft[ct] : 0.0;
-    return d2{a0, a1};
-  };
+  const int64_t n = J.n;
   const int ldf = J.ldf;
-  d4 acc[4][ET + 1];
-  mfma_dots<ET, false>(loadA, J.Z, ldf, noct, wave, lane, acc);
+  const int64_t col = col0 + lane < J.ncols ? col0 + lane : col0;
+  const int8_t* __restrict__ x = J.X + col * J.ldx;
+  const double* __restrict__ Z = J.Z;
+  const bool vec = ((reinterpret_cast<uintptr_t>(J.X) | (uintptr_t)J.ldx) & 15) == 0;
+  const int64_t seg = (n + 16 * XZ_WAVES - 1) / (16 * XZ_WAVES) * 16;
+  const int64_t r0 = (int64_t)wave * seg, r1 = r0 + seg < n ? r0 + seg : n;
+  double acc[LDFMAX];
 #pragma unroll
-  for (int et = 0; et < ET; et++) reduce_slice<ET>(acc, et, wave, lane, red, dots, ldf, 0, 0);
-  for (int idx = threadIdx.x; idx < AS_COLS * ldf; idx += 64 * AS_WAVES) {
-    const int c = idx / ldf, e = idx % ldf;
-    if (col0 + c < J.ncols) J.XZ[(col0 + c) * ldf + e] = dots[c][e];
+  for (int e = 0; e < LDFMAX; e++) acc[e] = 0.0;
+  int s = 0;
+  // 16 genotypes of the lane's column times 16 rows of Z (every one of the
+  // LDFMAX entries of a row is read: Z carries LDFMAX doubles of padding past
+  // its last row, and the products past ldf are never used).  The rows of Z
+  // go to scalar registers RG at a time, so that no more than about 80 of
+  // them hold rows in flight.
+  constexpr int RG = LDFMAX <= 4 ? 16 : LDFMAX <= 8 ? 4 : LDFMAX <= 20 ? 2 : 1;
+  auto step = [&](int64_t row, const int (&g)[16]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int i = 0; i < 16; i++) {
+      s += g[i];
+      const double xi = (double)g[i];
+      const double* __restrict__ zr = Z + (row + i) * ldf;
+#pragma unroll
+      for (int e = 0; e < LDFMAX; e++) acc[e] = fma(xi, zr[e], acc[e]);
+      if ((i + 1) % RG == 0) __builtin_amdgcn_sched_barrier(0);
+    }
+  };
+  auto unpack = [](const uint4& v, int (&g)[16]) __attribute__((always_inline)) {
+    const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int i = 0; i < 16; i++) g[i] = (int)(int8_t)(w4[i / 4] >> (8 * (i % 4)));
+  };
+  int64_t row = r0;
+  if (vec && row + 16 <= r1) {
+    // the next 16 genotypes are loaded while the current ones are used
+    uint4 nxt = *reinterpret_cast<const uint4*>(x + row);
+    for (; row + 16 <= r1; row += 16) {
+      const uint4 cur = nxt;
+      if (row + 32 <= r1) nxt = *reinterpret_cast<const uint4*>(x + row + 16);
+      int g[16];
+      unpack(cur, g);
+      step(row, g);
+    }
   }
+  for (; row < r1; row += 16) {
+    // unaligned genotypes, or the rows past the last full 16 (0 past r1,
+    // with Z rows that exist: r1 <= n rounded up to 16 <= n_pad)
+    int g[16];
+#pragma unroll
+    for (int i = 0; i < 16; i++) g[i] = row + i < r1 ? (int)x[row + i] : 0;
+    step(row, g);
+  }
+  isum[wave][lane] = s;
+  // the segments' partial products, four entries at a time, summed in wave
+  // order by the wave that owns the entry
+#pragma unroll
+  for (int e0 = 0; e0 < LDFMAX; e0 += 4) {
+#pragma unroll
+    for (int q = 0; q < 4; q++) part[wave][q][lane] = e0 + q < LDFMAX ? acc[e0 + q] : 0.0;
+    __syncthreads();
+    if (wave < 4 && e0 + wave < ldf) {
+      int tot = 0;
+      for (int w = 0; w < XZ_WAVES; w++) tot += isum[w][lane];
+      const double shift = rint(256.0 * (double)tot / (double)n) / 256.0;
+      double v = 0.0;
+      for (int w = 0; w < XZ_WAVES; w++) v += part[w][wave][lane];
+      if (col0 + lane < J.ncols) {
+        J.XZ[(col0 + lane) * ldf + e0 + wave] = v - shift * J.z1[e0 + wave];
+        if (e0 == 0 && wave == 0) J.shift[col0 + lane] = shift;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// z1 = 1^T Z (column sums of Z over its n rows): one work-group per column,
+// fixed-order reduction.
+__global__ __launch_bounds__(256) void k_colsum(const double* __restrict__ Z, int64_t n, int ld,
+                                                double* __restrict__ z1) {
+  const int e = blockIdx.x;
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int64_t r = threadIdx.x; r < n; r += 256) s += Z[r * ld + e];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) z1[e] = red[0];
 }
 
 
@@ -427,11 +452,20 @@ hipError_t launch_assemble_solve(const AsmTable& tab, int64_t ngroups, bool refi
 }
 
 hipError_t launch_xz_shift(const XzTable& tab, int64_t ngroups, hipStream_t st) {
-  int w = 1;
+  int w = 1;  // widest Z = M^{-1}[X_L | Y] of the table
   for (int i = 0; i < tab.njobs; i++) w = std::max(w, tab.j[i].ldf);
-  const unsigned g = (unsigned)ngroups, nt = 64 * AS_WAVES;
-  if (w <= 16) k_xz_shift<1><<<g, nt, 0, st>>>(tab);
-  else k_xz_shift<2><<<g, nt, 0, st>>>(tab);
+  const unsigned g = (unsigned)ngroups, nt = 64 * XZ_WAVES;
+  if (w <= 4) k_xz_shift<4><<<g, nt, 0, st>>>(tab);
+  else if (w <= 8) k_xz_shift<8><<<g, nt, 0, st>>>(tab);
+  else if (w <= 16) k_xz_shift<16><<<g, nt, 0, st>>>(tab);
+  else if (w <= 20) k_xz_shift<20><<<g, nt, 0, st>>>(tab);
+  else if (w <= MAXP + MAXT) k_xz_shift<MAXP + MAXT><<<g, nt, 0, st>>>(tab);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_colsum(const double* Z, int64_t n, int ld, double* z1, hipStream_t st) {
+  k_colsum<<<(unsigned)ld, 256, 0, st>>>(Z, n, ld, z1);
   return hipGetLastError();
 }
 

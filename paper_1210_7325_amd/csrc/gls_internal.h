@@ -75,6 +75,7 @@ struct XzDesc {
   const int8_t* X;
   int64_t ldx;
   const double* Z;          // row-major n_pad x ldf: M^{-1}[X_L | Y]
+  const double* z1;         // ldf column sums of Z over its n rows
   double* shift;            // out: ncols
   double* XZ;               // out: ncols x ldf
   int ldf;
@@ -103,5 +104,6 @@ hipError_t launch_gram(const double* F, int64_t n, int pL, int t, double* STL, d
 hipError_t launch_assemble_solve(const AsmTable& tab, int64_t ngroups, bool refine, hipStream_t st);
 hipError_t launch_trsm_mixed(const JobTable& tab, int64_t nslabs, int C, hipStream_t st);
 hipError_t launch_xz_shift(const XzTable& tab, int64_t ngroups, hipStream_t st);
+hipError_t launch_colsum(const double* Z, int64_t n, int ld, double* z1, hipStream_t st);
 
 }  // namespace gls

@@ -362,3 +362,24 @@ def test_layout_copies_are_ordered_on_the_handle_stream(G):
         assert maxrel(c.copy_factor().cpu().numpy(), Lref) < TOL_MID
         assert orc.relative_error(B.cpu().numpy(), ref).max() < TOL_B
         c.free()
+
+
+def test_workspace_regrowth_after_launch_on_another_stream(G):
+    """A block solved through gls_solve_multi on a stream other than the
+    handle's, then a larger block on the handle's own stream (the workspace
+    grows while the first launch may still read it): both results match the
+    oracle."""
+    say("workspace regrowth across streams")
+    w, M, XL, Y, XR = small_problem(900, m=3000, seed=5)
+    c = G.Cohort(to_dev(M)).whiten_fixed(to_dev(XL), to_dev(Y))
+    dXR = to_dev(XR)
+    other = torch.cuda.Stream()
+    Ba = torch.empty((200, 1, 4), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    G.solve_multi([(c, dXR[:, :200], 1, Ba, None)], stream=other)
+    Bb, _ = c.solve_block(dXR, p_R=1)          # 3000 columns: the workspace grows
+    torch.cuda.synchronize()
+    ref = orc.gls_sequence(M, XL, XR, Y, 1)
+    assert orc.relative_error(Ba.cpu().numpy(), ref[:200]).max() < 1e-10
+    assert orc.relative_error(Bb.cpu().numpy(), ref).max() < 1e-10
+    c.free()
