@@ -72,6 +72,9 @@ def parse():
                     help="offered load of the Poisson arrivals, relative to 50 TFLOP/s")
     ap.add_argument("--serve-m-max", type=float, default=2e6,
                     help="upper end of the log-uniform m range (the full mix uses 1e7)")
+    ap.add_argument("--serve-ingest", choices=("host", "device"), default="host",
+                    help="serving: job genotypes produced on the host and copied through pinned "
+                         "staging (host), or generated in device memory (device)")
     ap.add_argument("--stream-source", choices=("generator", "file"), default="generator",
                     help="stream workload: genotypes from the host generator or from a file "
                          "read by the library's reader (written first, removed after)")
@@ -826,9 +829,11 @@ def serve_bench(args):
     res = {}
     for prec in args.forms.split(","):
         jobs = serve.make_jobs(args.serve_jobs, rate=rate, m_range=(1e5, args.serve_m_max))
-        ex = serve.GpuExecutor(precision=prec, phi=phi)
-        stats = serve.Scheduler(ex, budget_bytes=200 << 30,
+        ex = serve.GpuExecutor(precision=prec, phi=phi, ingest=args.serve_ingest)
+        stats = serve.Scheduler(ex, budget_bytes=(200 << 30) - ex.staging_bytes(),
                                 log=lambda msg, prec=prec: log(f"[{prec}] {msg}")).run(jobs)
+        stats["timeline"] = ex.timeline_summary()
+        log(f"[{prec}] timeline: {stats['timeline']}")
         stats["jobs_detail"] = [(j.id, j.n, j.p, j.m, round(j.arrival, 3), round(j.finished - j.arrival, 3)
                                  if j.finished is not None else None, j.state, j.error) for j in jobs]
         res[prec] = stats
@@ -844,7 +849,8 @@ def serve_bench(args):
         "config": {"workload": "serving_mix", "jobs": args.serve_jobs, "arrival_rate": rate,
                    "offered_load_at_50TF": args.serve_load, "n": [1500, 4000, 10000, 20000],
                    "p": [4, 20], "m": [1e5, args.serve_m_max], "h": [0.2, 0.8],
-                   "hbm_budget_bytes": 200 << 30, "parallelism": "1 GPU"},
+                   "hbm_budget_bytes": 200 << 30, "ingest": args.serve_ingest,
+                   "parallelism": "1 GPU"},
         "forms": res,
     }
     print(json.dumps(out), flush=True)

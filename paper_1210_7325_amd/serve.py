@@ -15,6 +15,14 @@ Each job's blocks are sized so that all items of a round cost about the
 same (block ~ n^-2), and a job's results do not depend on what it was
 batched with (bitwise).
 
+A job's genotypes reach the device through host memory, as they would from
+a job's files: for every round the executor produces the items' genotype
+blocks on the host (the C generator stands in for the job's source) into a
+pinned staging slot, copies the slot to the device on a copy stream, and
+the compute stream waits for that copy before the round's launches; with
+three slots, the host production and the copy of the next round overlap the
+device work of the previous ones, and job latency includes the ingestion.
+
 The scheduler is plain Python logic over an executor interface; `GpuExecutor`
 drives libgls.so, and tests drive the scheduler with a fake executor.
 """
@@ -97,6 +105,32 @@ class Executor:
     def submit_round(self, items: List[tuple]) -> object:
         """items: (job, snp0, nsnp); returns a token for poll/wait."""
         raise NotImplementedError
+
+    def timeline_summary(self) -> Dict:
+        """Rounds as the device ran them: time inside rounds, whitening rate
+        inside rounds, and the gaps between consecutive rounds when the
+        second was already queued (launch and ingestion overhead: what a
+        persistent launch could recover), apart from the gaps when the
+        device had nothing to do (waiting for arrivals)."""
+        self.stream.synchronize()
+        busy = queued_gap = idle_gap = work = 0.0
+        prev = None
+        for (a, b, w, behind) in self.timeline:
+            busy += a.elapsed_time(b) * 1e-3
+            work += w
+            if prev is not None:
+                g = max(0.0, prev.elapsed_time(a) * 1e-3)
+                if behind:
+                    queued_gap += g
+                else:
+                    idle_gap += g
+            prev = b
+        return {"rounds": len(self.timeline), "device_in_rounds_s": busy,
+                "round_whitening_tflops": work / max(busy, 1e-12) / 1e12,
+                "queued_gap_s": queued_gap, "idle_gap_s": idle_gap,
+                "queued_gap_frac_of_busy": queued_gap / max(busy, 1e-12),
+                "ingest_host_s": self.ingest_host_s, "ingest_gb": self.ingest_bytes / 1e9,
+                "ingest": self.ingest}
 
     def poll(self, token) -> bool:
         raise NotImplementedError
@@ -183,8 +217,13 @@ class Scheduler:
                     pick = [ready[(rr + i) % k] for i in range(min(k, self.max_items))]
                     base = sum(j.block for j in pick)
                     mult = max(1, min(self.max_mult, -(-self.target_cols // base)))
+                    # genotype bytes of a round are bounded by the executor's
+                    # staging (a share per item, so that every picked job gets one)
+                    cap = getattr(self.ex, "max_round_bytes", None)
                     for j in pick:
                         nsnp = min(j.block * mult, j.max_block, j.m - j.submitted)
+                        if cap:
+                            nsnp = max(1, min(nsnp, cap // len(pick) // j.n))
                         items.append((j, j.submitted, nsnp))
                         j.submitted += nsnp
                     rr = (rr + len(items)) % max(k, 1)
@@ -256,23 +295,56 @@ class GpuExecutor(Executor):
     Per job: M = h*Phi_n + (1-h)*I + 1e-3*I built on the device from a
     resident Phi per cohort size (input construction), factored by
     gls_factor on the job's own stream, the fixed part whitened, one handle
-    whose workspace holds one block, a device buffer for the job's genotype
-    block (filled by the device generator before each round) and the job's
-    output b (m x p, on the device).  Rounds run on one compute stream."""
+    whose workspace holds one block, and the job's output b (m x p, on the
+    device).  Genotypes: per round, the items' blocks are produced on the
+    host into a pinned staging slot and copied to the slot's device buffer
+    on a copy stream (`ingest="host"`, the default), or generated directly in
+    device memory by the device twin of the generator (`ingest="device"`,
+    no transfer).  Rounds run on one compute stream."""
+
+    SLOTS = 3
 
     def __init__(self, precision: str = "fp64", phi: Optional[Dict[int, object]] = None,
-                 keep_results: bool = False):
+                 keep_results: bool = False, ingest: str = "host",
+                 slot_bytes: int = 1 << 30):
         import torch
         from . import gls
         self.torch, self.gls = torch, gls
         gls.lib()
-        dg._dlib()
+        assert ingest in ("host", "device")
+        self.ingest = ingest
+        if ingest == "device":
+            dg._dlib()
         self.precision = precision
         self.stream = torch.cuda.Stream()
+        self.copy_stream = torch.cuda.Stream()
         self.phi = phi if phi is not None else {}
         self.state = {}
         self.keep_results = keep_results
         self.results = {}
+        # (slack for the 256-byte alignment of each item in a slot)
+        self.max_round_bytes = slot_bytes - (1 << 20) if ingest == "host" else None
+        # staging slots: pinned host buffer, device buffer, and the events
+        # that free them (copy done: pinned reusable; round done: device
+        # buffer reusable)
+        self.slots = []
+        if ingest == "host":
+            for _ in range(self.SLOTS):
+                self.slots.append({
+                    "host": torch.empty(slot_bytes, dtype=torch.int8).pin_memory(),
+                    "dev": torch.empty(slot_bytes, dtype=torch.int8, device="cuda"),
+                    "copied": torch.cuda.Event(), "done": torch.cuda.Event()})
+        self.round_no = 0
+        self.ingest_host_s = 0.0    # host time producing genotypes
+        self.ingest_bytes = 0
+        # device timeline of the rounds: (start event, end event, whitening
+        # flops, whether the previous round was still on the device when
+        # this one was submitted)
+        self.timeline = []
+
+    def staging_bytes(self) -> int:
+        """Device memory the executor holds besides the jobs' footprints."""
+        return sum(int(sl["dev"].numel()) for sl in self.slots)
 
     def _phi(self, n: int):
         if n not in self.phi:
@@ -284,7 +356,8 @@ class GpuExecutor(Executor):
         p = self.gls.PRECISIONS[self.precision]
         blk = job.max_block or job.block or job_block(job.n)
         b = self.gls.gls_footprint_bytes(job.n, job.p_L, 1, 1, blk, p)
-        b += job.n * blk                                       # genotype block
+        if self.ingest == "device":
+            b += job.n * blk                                   # genotype block
         b += job.m * job.p * 8 + job.m * 4                     # b and info
         b += job.n * job.n * 8                                 # M while factoring
         return int(b)
@@ -308,7 +381,9 @@ class GpuExecutor(Executor):
         blk = job.max_block or job.block
         c.reserve(blk)
         s.synchronize()
-        xbuf = torch.empty((blk, job.n), dtype=torch.int8, device="cuda").t()
+        xbuf = None
+        if self.ingest == "device":
+            xbuf = torch.empty((blk, job.n), dtype=torch.int8, device="cuda").t()
         B = torch.empty((job.m, 1, job.p), dtype=torch.float64, device="cuda")
         info = torch.empty((job.m,), dtype=torch.int32, device="cuda")
         self.state[job.id] = (c, xbuf, B, info, w)
@@ -317,17 +392,54 @@ class GpuExecutor(Executor):
         torch, gls = self.torch, self.gls
         sp = self.stream.cuda_stream
         works = []
-        for (job, s0, nsnp) in items:
-            c, xbuf, B, info, w = self.state[job.id]
-            dg.make_XR_device(w, s0, nsnp, xbuf, sp)
-            works.append(gls.gls_work(c.h, nsnp, 1, xbuf.data_ptr(), job.n,
-                                      B[s0:s0 + nsnp].data_ptr(), job.p,
-                                      info[s0:s0 + nsnp].data_ptr()))
+        behind = bool(self.timeline) and not self.timeline[-1][1].query()
+        if self.ingest == "device":
+            for (job, s0, nsnp) in items:
+                c, xbuf, B, info, w = self.state[job.id]
+                dg.make_XR_device(w, s0, nsnp, xbuf, sp)
+                works.append(gls.gls_work(c.h, nsnp, 1, xbuf.data_ptr(), job.n,
+                                          B[s0:s0 + nsnp].data_ptr(), job.p,
+                                          info[s0:s0 + nsnp].data_ptr()))
+        else:
+            slot = self.slots[self.round_no % len(self.slots)]
+            # the pinned buffer is free once its previous copy has landed
+            slot["copied"].synchronize()
+            t0 = time.perf_counter()
+            off, offs = 0, []
+            for (job, s0, nsnp) in items:
+                c, xbuf, B, info, w = self.state[job.id]
+                nb = job.n * nsnp
+                assert off + nb <= slot["host"].numel(), "round exceeds the staging slot"
+                view = slot["host"][off:off + nb].view(nsnp, job.n).numpy()
+                dg.make_XR(w, s0, nsnp, out=view)          # the job's genotypes, on the host
+                offs.append(off)
+                off = (off + nb + 255) // 256 * 256
+            self.ingest_host_s += time.perf_counter() - t0
+            self.ingest_bytes += off
+            # the device buffer is free once the round that used it has finished
+            self.copy_stream.wait_event(slot["done"])
+            with torch.cuda.stream(self.copy_stream):
+                slot["dev"][:off].copy_(slot["host"][:off], non_blocking=True)
+            slot["copied"].record(self.copy_stream)
+            self.stream.wait_event(slot["copied"])
+            base = slot["dev"].data_ptr()
+            for (job, s0, nsnp), o in zip(items, offs):
+                c, xbuf, B, info, w = self.state[job.id]
+                works.append(gls.gls_work(c.h, nsnp, 1, base + o, job.n,
+                                          B[s0:s0 + nsnp].data_ptr(), job.p,
+                                          info[s0:s0 + nsnp].data_ptr()))
+        t_start = torch.cuda.Event(enable_timing=True)
+        t_start.record(self.stream)
         rc = gls.gls_solve_multi(works, sp)
         if rc != 0:
             raise gls.GLSError(rc, "gls_solve_multi")
-        ev = torch.cuda.Event()
+        ev = torch.cuda.Event(enable_timing=True)
         ev.record(self.stream)
+        self.timeline.append((t_start, ev, sum(float(job.n) ** 2 * nsnp for (job, _, nsnp) in items),
+                              behind))
+        if self.ingest == "host":
+            slot["done"].record(self.stream)
+            self.round_no += 1
         return ev
 
     def poll(self, token) -> bool:
