@@ -72,6 +72,10 @@ def parse():
                     help="offered load of the Poisson arrivals, relative to 50 TFLOP/s")
     ap.add_argument("--serve-m-max", type=float, default=2e6,
                     help="upper end of the log-uniform m range (the full mix uses 1e7)")
+    ap.add_argument("--serve-streams", type=int, default=2,
+                    help="serving: compute streams the rounds alternate over")
+    ap.add_argument("--serve-inflight", type=int, default=4,
+                    help="serving: rounds queued on the device at once")
     ap.add_argument("--serve-ingest", choices=("host", "device"), default="host",
                     help="serving: job genotypes produced on the host and copied through pinned "
                          "staging (host), or generated in device memory (device)")
@@ -829,8 +833,10 @@ def serve_bench(args):
     res = {}
     for prec in args.forms.split(","):
         jobs = serve.make_jobs(args.serve_jobs, rate=rate, m_range=(1e5, args.serve_m_max))
-        ex = serve.GpuExecutor(precision=prec, phi=phi, ingest=args.serve_ingest)
+        ex = serve.GpuExecutor(precision=prec, phi=phi, ingest=args.serve_ingest,
+                               streams=args.serve_streams, slots=args.serve_inflight + 1)
         stats = serve.Scheduler(ex, budget_bytes=(200 << 30) - ex.staging_bytes(),
+                                inflight=args.serve_inflight,
                                 log=lambda msg, prec=prec: log(f"[{prec}] {msg}")).run(jobs)
         stats["timeline"] = ex.timeline_summary()
         log(f"[{prec}] timeline: {stats['timeline']}")
@@ -850,6 +856,7 @@ def serve_bench(args):
                    "offered_load_at_50TF": args.serve_load, "n": [1500, 4000, 10000, 20000],
                    "p": [4, 20], "m": [1e5, args.serve_m_max], "h": [0.2, 0.8],
                    "hbm_budget_bytes": 200 << 30, "ingest": args.serve_ingest,
+                   "compute_streams": args.serve_streams, "rounds_inflight": args.serve_inflight,
                    "parallelism": "1 GPU"},
         "forms": res,
     }

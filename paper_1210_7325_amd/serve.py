@@ -8,8 +8,12 @@ takes the next block of problems from each active job and solves all of
 them with ONE launch of the whitening kernel and one of the assembly/solve
 kernel (gls_solve_multi).  Jobs that arrive while others run are admitted as
 soon as memory frees up and their blocks join the next round, so the work of
-different jobs overlaps on the device.  Rounds are queued on one stream, two
-deep, so the device never waits for the host between rounds.
+different jobs overlaps on the device.  Rounds are queued four deep and
+alternate over two compute streams, so the device never waits for the host
+between rounds and the next round's work-groups take the compute units that
+the previous round's last slabs leave free (rounds overlap on the device as
+items of one persistent launch would, without a device-wide barrier between
+them).
 
 Each job's blocks are sized so that all items of a round cost about the
 same (block ~ n^-2), and a job's results do not depend on what it was
@@ -106,32 +110,6 @@ class Executor:
         """items: (job, snp0, nsnp); returns a token for poll/wait."""
         raise NotImplementedError
 
-    def timeline_summary(self) -> Dict:
-        """Rounds as the device ran them: time inside rounds, whitening rate
-        inside rounds, and the gaps between consecutive rounds when the
-        second was already queued (launch and ingestion overhead: what a
-        persistent launch could recover), apart from the gaps when the
-        device had nothing to do (waiting for arrivals)."""
-        self.stream.synchronize()
-        busy = queued_gap = idle_gap = work = 0.0
-        prev = None
-        for (a, b, w, behind) in self.timeline:
-            busy += a.elapsed_time(b) * 1e-3
-            work += w
-            if prev is not None:
-                g = max(0.0, prev.elapsed_time(a) * 1e-3)
-                if behind:
-                    queued_gap += g
-                else:
-                    idle_gap += g
-            prev = b
-        return {"rounds": len(self.timeline), "device_in_rounds_s": busy,
-                "round_whitening_tflops": work / max(busy, 1e-12) / 1e12,
-                "queued_gap_s": queued_gap, "idle_gap_s": idle_gap,
-                "queued_gap_frac_of_busy": queued_gap / max(busy, 1e-12),
-                "ingest_host_s": self.ingest_host_s, "ingest_gb": self.ingest_bytes / 1e9,
-                "ingest": self.ingest}
-
     def poll(self, token) -> bool:
         raise NotImplementedError
 
@@ -146,7 +124,7 @@ class Scheduler:
     """Admission by footprint, round composition, completion bookkeeping."""
 
     def __init__(self, executor: Executor, budget_bytes: int, max_items: int = 16,
-                 inflight: int = 2, clock=time.monotonic, sleep=time.sleep,
+                 inflight: int = 4, clock=time.monotonic, sleep=time.sleep,
                  target_cols: int = 16384, max_mult: int = 16, log=None):
         self.ex = executor
         self.budget = int(budget_bytes)
@@ -302,11 +280,9 @@ class GpuExecutor(Executor):
     device memory by the device twin of the generator (`ingest="device"`,
     no transfer).  Rounds run on one compute stream."""
 
-    SLOTS = 3
-
     def __init__(self, precision: str = "fp64", phi: Optional[Dict[int, object]] = None,
                  keep_results: bool = False, ingest: str = "host",
-                 slot_bytes: int = 1 << 30):
+                 slot_bytes: int = 1 << 30, streams: int = 2, slots: int = 5):
         import torch
         from . import gls
         self.torch, self.gls = torch, gls
@@ -316,7 +292,12 @@ class GpuExecutor(Executor):
         if ingest == "device":
             dg._dlib()
         self.precision = precision
-        self.stream = torch.cuda.Stream()
+        # rounds alternate over `streams` compute streams, so that the next
+        # round's work-groups take the compute units the previous round's
+        # last slabs leave free (no device-wide barrier between rounds); a
+        # job keeps one handle (workspace) per stream
+        self.streams = [torch.cuda.Stream() for _ in range(streams)]
+        self.stream = self.streams[0]
         self.copy_stream = torch.cuda.Stream()
         self.phi = phi if phi is not None else {}
         self.state = {}
@@ -329,7 +310,7 @@ class GpuExecutor(Executor):
         # buffer reusable)
         self.slots = []
         if ingest == "host":
-            for _ in range(self.SLOTS):
+            for _ in range(slots):
                 self.slots.append({
                     "host": torch.empty(slot_bytes, dtype=torch.int8).pin_memory(),
                     "dev": torch.empty(slot_bytes, dtype=torch.int8, device="cuda"),
@@ -356,6 +337,8 @@ class GpuExecutor(Executor):
         p = self.gls.PRECISIONS[self.precision]
         blk = job.max_block or job.block or job_block(job.n)
         b = self.gls.gls_footprint_bytes(job.n, job.p_L, 1, 1, blk, p)
+        # the workspaces of the handles forked for the other streams
+        b += (len(self.streams) - 1) * (b - self.gls.gls_footprint_bytes(job.n, job.p_L, 1, 1, 0, p))
         if self.ingest == "device":
             b += job.n * blk                                   # genotype block
         b += job.m * job.p * 8 + job.m * 4                     # b and info
@@ -380,24 +363,33 @@ class GpuExecutor(Executor):
         c.whiten_fixed(XL, Y, intercept_col=0)
         blk = job.max_block or job.block
         c.reserve(blk)
+        hs = [c]
+        for st in self.streams[1:]:
+            f = c.fork(st)
+            f.reserve(blk)
+            hs.append(f)
         s.synchronize()
         xbuf = None
         if self.ingest == "device":
             xbuf = torch.empty((blk, job.n), dtype=torch.int8, device="cuda").t()
         B = torch.empty((job.m, 1, job.p), dtype=torch.float64, device="cuda")
         info = torch.empty((job.m,), dtype=torch.int32, device="cuda")
-        self.state[job.id] = (c, xbuf, B, info, w)
+        self.state[job.id] = (hs, xbuf, B, info, w)
 
     def submit_round(self, items):
         torch, gls = self.torch, self.gls
-        sp = self.stream.cuda_stream
+        k = self.round_no % len(self.streams)
+        stream = self.streams[k]
+        sp = stream.cuda_stream
         works = []
         behind = bool(self.timeline) and not self.timeline[-1][1].query()
         if self.ingest == "device":
             for (job, s0, nsnp) in items:
-                c, xbuf, B, info, w = self.state[job.id]
+                hs, xbuf, B, info, w = self.state[job.id]
+                # one genotype buffer per job: its rounds stay on one stream
+                stream, sp, k = self.streams[0], self.streams[0].cuda_stream, 0
                 dg.make_XR_device(w, s0, nsnp, xbuf, sp)
-                works.append(gls.gls_work(c.h, nsnp, 1, xbuf.data_ptr(), job.n,
+                works.append(gls.gls_work(hs[k].h, nsnp, 1, xbuf.data_ptr(), job.n,
                                           B[s0:s0 + nsnp].data_ptr(), job.p,
                                           info[s0:s0 + nsnp].data_ptr()))
         else:
@@ -407,7 +399,7 @@ class GpuExecutor(Executor):
             t0 = time.perf_counter()
             off, offs = 0, []
             for (job, s0, nsnp) in items:
-                c, xbuf, B, info, w = self.state[job.id]
+                hs, xbuf, B, info, w = self.state[job.id]
                 nb = job.n * nsnp
                 assert off + nb <= slot["host"].numel(), "round exceeds the staging slot"
                 view = slot["host"][off:off + nb].view(nsnp, job.n).numpy()
@@ -421,26 +413,63 @@ class GpuExecutor(Executor):
             with torch.cuda.stream(self.copy_stream):
                 slot["dev"][:off].copy_(slot["host"][:off], non_blocking=True)
             slot["copied"].record(self.copy_stream)
-            self.stream.wait_event(slot["copied"])
+            stream.wait_event(slot["copied"])
             base = slot["dev"].data_ptr()
             for (job, s0, nsnp), o in zip(items, offs):
-                c, xbuf, B, info, w = self.state[job.id]
-                works.append(gls.gls_work(c.h, nsnp, 1, base + o, job.n,
+                hs, xbuf, B, info, w = self.state[job.id]
+                works.append(gls.gls_work(hs[k].h, nsnp, 1, base + o, job.n,
                                           B[s0:s0 + nsnp].data_ptr(), job.p,
                                           info[s0:s0 + nsnp].data_ptr()))
         t_start = torch.cuda.Event(enable_timing=True)
-        t_start.record(self.stream)
+        t_start.record(stream)
         rc = gls.gls_solve_multi(works, sp)
         if rc != 0:
             raise gls.GLSError(rc, "gls_solve_multi")
         ev = torch.cuda.Event(enable_timing=True)
-        ev.record(self.stream)
+        ev.record(stream)
         self.timeline.append((t_start, ev, sum(float(job.n) ** 2 * nsnp for (job, _, nsnp) in items),
                               behind))
         if self.ingest == "host":
-            slot["done"].record(self.stream)
-            self.round_no += 1
+            slot["done"].record(stream)
+        self.round_no += 1
         return ev
+
+    def timeline_summary(self) -> Dict:
+        """Rounds as the device ran them.  device_busy_s: time with at least
+        one round on the device (rounds on different streams may overlap;
+        overlap_s is the time they did); round_whitening_tflops: whitening
+        rate over that time; queued_gap_s: time between rounds when the next
+        one had been submitted before the previous finished (launch and
+        ingestion overhead, what a persistent launch could recover);
+        idle_gap_s: time the device waited for arrivals."""
+        for st in self.streams:
+            st.synchronize()
+        if not self.timeline:
+            return {"rounds": 0}
+        t0 = self.timeline[0][0]
+        iv = sorted((t0.elapsed_time(a) * 1e-3, t0.elapsed_time(b) * 1e-3, w, behind)
+                    for (a, b, w, behind) in self.timeline)
+        busy = queued_gap = idle_gap = 0.0
+        cur_s, cur_e = iv[0][0], iv[0][1]
+        for (s0, e0, _, behind) in iv[1:]:
+            if s0 > cur_e:
+                if behind:
+                    queued_gap += s0 - cur_e
+                else:
+                    idle_gap += s0 - cur_e
+                busy += cur_e - cur_s
+                cur_s, cur_e = s0, e0
+            else:
+                cur_e = max(cur_e, e0)
+        busy += cur_e - cur_s
+        work = sum(x[2] for x in iv)
+        total = sum(x[1] - x[0] for x in iv)
+        return {"rounds": len(iv), "streams": len(self.streams), "device_busy_s": busy,
+                "round_whitening_tflops": work / max(busy, 1e-12) / 1e12,
+                "overlap_s": total - busy, "queued_gap_s": queued_gap, "idle_gap_s": idle_gap,
+                "queued_gap_frac_of_busy": queued_gap / max(busy, 1e-12),
+                "ingest_host_s": self.ingest_host_s, "ingest_gb": self.ingest_bytes / 1e9,
+                "ingest": self.ingest}
 
     def poll(self, token) -> bool:
         return token.query()
@@ -449,7 +478,9 @@ class GpuExecutor(Executor):
         token.synchronize()
 
     def release(self, job: Job) -> None:
-        c, xbuf, B, info, w = self.state.pop(job.id)
+        hs, xbuf, B, info, w = self.state.pop(job.id)
         if self.keep_results:
             self.results[job.id] = (B.cpu().numpy(), info.cpu().numpy())
-        c.free()
+        for h in hs[1:]:
+            h.free()
+        hs[0].free()
