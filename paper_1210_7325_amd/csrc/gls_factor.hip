@@ -237,16 +237,25 @@ __global__ __launch_bounds__(256) void k_panel(double* __restrict__ A, int64_t l
             acc[rt][ct][i];
 }
 
-// Trailing update: A[r, s] -= A[r, k] A[s, k]^T for k < s <= r < K.
+// Trailing update: A[r, s] -= A[r, k] A[s, k]^T for s0 <= s <= r < K (one
+// work-group per tile): the whole lower triangle of column blocks s >= s0,
+// or (col_only) column block s0 alone.
 __global__ __launch_bounds__(256) void k_syrk(double* __restrict__ A, int64_t lda, int k, int K,
-                                              const int* __restrict__ info) {
+                                              int s0, int col_only, const int* __restrict__ info) {
   if (*info != 0) return;
   const int64_t t = blockIdx.x;
-  int i = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
-  while ((int64_t)(i + 1) * (i + 2) / 2 <= t) i++;
-  while ((int64_t)i * (i + 1) / 2 > t) i--;
-  const int j = (int)(t - (int64_t)i * (i + 1) / 2);
-  const int r = k + 1 + i, s = k + 1 + j;
+  int r, s;
+  if (col_only) {
+    r = s0 + (int)t;
+    s = s0;
+  } else {
+    int i = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while ((int64_t)(i + 1) * (i + 2) / 2 <= t) i++;
+    while ((int64_t)i * (i + 1) / 2 > t) i--;
+    const int j = (int)(t - (int64_t)i * (i + 1) / 2);
+    r = s0 + i;
+    s = s0 + j;
+  }
   if (r >= K) return;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int wr = wave / 2, wc = wave % 2;
@@ -339,17 +348,54 @@ hipError_t launch_factor(const double* M, int64_t ldm, int64_t n, int64_t n_pad,
     dim3 grid((unsigned)((n_pad + 255) / 256), (unsigned)(n_pad < 65535 ? n_pad : 65535));
     k_copy_pad<<<grid, 256, 0, st>>>(M, ldm, n, A, n_pad);
   }
-  for (int k = 0; k < K; k++) {
+  // Right-looking with a lookahead of one block column: step k updates the
+  // next column block k+1 first, on st, then the rest of the trailing matrix
+  // on a second stream, so that the diagonal step and the panel of k+1 (a
+  // sequential chain of small launches) run beside the large update of k.
+  // Before it updates column block k+1, step k waits for the rest-update of
+  // step k-1 (which also wrote that column); the last one is waited for
+  // before the packing.
+  hipStream_t s2 = nullptr;
+  hipEvent_t ev_panel = nullptr, ev_rest = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&s2, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_panel, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_rest, hipEventDisableTiming);
+  bool rest_pending = false;
+  for (int k = 0; k < K && e == hipSuccess; k++) {
     k_potf2_inv<<<1, 256, 0, st>>>(A, n_pad, k, n, Ldiag, Linv, dinfo);
-    if (k + 1 < K) {
-      k_panel<<<K - 1 - k, 256, 0, st>>>(A, n_pad, k, Linv, dinfo);
-      const int64_t d = K - 1 - k;
-      k_syrk<<<(unsigned)(d * (d + 1) / 2), 256, 0, st>>>(A, n_pad, k, K, dinfo);
+    if (k + 1 >= K) break;
+    k_panel<<<K - 1 - k, 256, 0, st>>>(A, n_pad, k, Linv, dinfo);
+    if (rest_pending) e = hipStreamWaitEvent(st, ev_rest, 0);
+    if (e != hipSuccess) break;
+    const int64_t d = K - 1 - k;
+    k_syrk<<<(unsigned)d, 256, 0, st>>>(A, n_pad, k, K, k + 1, 1, dinfo);
+    rest_pending = false;
+    if (d > 1) {
+      const int64_t d2 = d - 1;
+      e = hipEventRecord(ev_panel, st);
+      if (e == hipSuccess) e = hipStreamWaitEvent(s2, ev_panel, 0);
+      if (e != hipSuccess) break;
+      k_syrk<<<(unsigned)(d2 * (d2 + 1) / 2), 256, 0, s2>>>(A, n_pad, k, K, k + 2, 0, dinfo);
+      e = hipEventRecord(ev_rest, s2);
+      rest_pending = true;
     }
   }
-  const int64_t nblk = (int64_t)K * (K + 1) / 2;
-  k_pack<<<(unsigned)nblk, 256, 0, st>>>(A, n_pad, Linv, Lstrips, LinvP, Lstrips32, K);
-  return hipGetLastError();
+  if (e == hipSuccess && rest_pending) e = hipStreamWaitEvent(st, ev_rest, 0);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e == hipSuccess) {
+    const int64_t nblk = (int64_t)K * (K + 1) / 2;
+    k_pack<<<(unsigned)nblk, 256, 0, st>>>(A, n_pad, Linv, Lstrips, LinvP, Lstrips32, K);
+    e = hipGetLastError();
+  }
+  // the second stream's work is ordered before st's packing; its handles go
+  // once that work is done
+  if (s2) {
+    (void)hipStreamSynchronize(s2);
+    (void)hipStreamDestroy(s2);
+  }
+  if (ev_panel) (void)hipEventDestroy(ev_panel);
+  if (ev_rest) (void)hipEventDestroy(ev_rest);
+  return e;
 }
 
 hipError_t launch_unpack_factor(const double* Lstrips, const double* Ldiag, int64_t n, double* L,

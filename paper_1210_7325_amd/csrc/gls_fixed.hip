@@ -6,9 +6,9 @@ namespace gls {
 // ---------------------------------------------------------------------------
 // a1: the fixed part F = [X_L | Y] (p_L + t <= 27 columns, once per cohort),
 // row-major n_pad x w.  Triangular solves on it run right-looking with one
-// launch per row block: the diagonal step on block k, then the update of
-// every other affected block in parallel (one work-group per block, the
-// 128 x 128 block of L staged in LDS from its contiguous packed form).
+// launch per row block: the update of every affected block with block k in
+// parallel (one work-group per block), the next block's diagonal step done
+// by its own work-group at the end of the same launch.
 //   lower (F := L^{-1} F):  F_k = inv(L_kk) F_k;  F_j -= L_jk F_k  (j > k)
 //   upper (Z := L^{-T} Z):  Z_k = inv(L_kk)^T Z_k; Z_j -= L_kj^T Z_k (j < k)
 
@@ -75,12 +75,19 @@ __global__ __launch_bounds__(256) void k_fix_diag(const double* __restrict__ Lin
   }
 }
 
+// One step of the solve in a single launch: every work-group updates its
+// block j with block k (lower: F_j -= L_jk F_k, j > k; upper:
+// Z_j -= L_kj^T Z_k, j < k; the 128 x 128 block of L staged in LDS from its
+// contiguous packed form), and the one whose block is the
+// next to be finished (j = k + 1 for the lower solve, j = k - 1 for the
+// upper one) then applies that block's diagonal step (as k_fix_diag), so
+// that the next launch can use it.  K - 1 launches instead of 2K - 1.
 template <bool UPPER>
-__global__ __launch_bounds__(256) void k_fix_update(const double* __restrict__ Lstrips, int k,
-                                                    double* __restrict__ F, int w) {
+__global__ __launch_bounds__(256) void k_fix_step(const double* __restrict__ Lstrips,
+                                                  const double* __restrict__ LinvP, int k,
+                                                  double* __restrict__ F, int w) {
   __shared__ double T[NB][NB + 1];
   const int j = UPPER ? (int)blockIdx.x : k + 1 + (int)blockIdx.x;
-  // lower: block L_jk (strip j, block column k); upper: block L_kj (strip k, column j)
   const double* blk = UPPER ? Lstrips + strip_offset(k) + (size_t)j * NB * NB
                             : Lstrips + strip_offset(j) + (size_t)k * NB * NB;
   stage_block(T, blk);
@@ -92,6 +99,19 @@ __global__ __launch_bounds__(256) void k_fix_update(const double* __restrict__ L
   for (int ci = 0; ci < FIX_COLS_PER_THREAD; ci++) {
     const int c = half + 2 * ci;
     if (c < w) F[((int64_t)j * NB + a) * w + c] -= acc[ci];
+  }
+  if (j != (UPPER ? k - 1 : k + 1)) return;
+  // block j is now final but for its diagonal step: every thread's update is
+  // visible to the work-group, and T is free, after the barrier
+  __syncthreads();
+  stage_block(T, LinvP + (size_t)j * NB * NB);
+  __syncthreads();
+  fix_product<UPPER>(T, F, (int64_t)j * NB, w, a, half, true, acc);
+  __syncthreads();  // every read of block j happens before it is overwritten
+#pragma unroll
+  for (int ci = 0; ci < FIX_COLS_PER_THREAD; ci++) {
+    const int c = half + 2 * ci;
+    if (c < w) F[((int64_t)j * NB + a) * w + c] = acc[ci];
   }
 }
 
@@ -132,17 +152,13 @@ hipError_t launch_fixed_solve(const double* XL, int64_t ldx, const double* Y, in
   const int w = pL + t;
   const int64_t total = n_pad * w;
   k_pack_fixed<<<(unsigned)((total + 255) / 256), 256, 0, st>>>(XL, ldx, Y, ldy, n, n_pad, pL, t, F);
-  for (int k = 0; k < K; k++) {
-    k_fix_diag<false><<<1, 256, 0, st>>>(LinvP, k, F, w);
-    if (k + 1 < K) k_fix_update<false><<<K - 1 - k, 256, 0, st>>>(Lstrips, k, F, w);
-  }
+  k_fix_diag<false><<<1, 256, 0, st>>>(LinvP, 0, F, w);
+  for (int k = 0; k + 1 < K; k++) k_fix_step<false><<<K - 1 - k, 256, 0, st>>>(Lstrips, LinvP, k, F, w);
   if (Z) {
     hipError_t e = hipMemcpyAsync(Z, F, sizeof(double) * total, hipMemcpyDeviceToDevice, st);
     if (e != hipSuccess) return e;
-    for (int k = K - 1; k >= 0; k--) {
-      k_fix_diag<true><<<1, 256, 0, st>>>(LinvP, k, Z, w);
-      if (k > 0) k_fix_update<true><<<k, 256, 0, st>>>(Lstrips, k, Z, w);
-    }
+    k_fix_diag<true><<<1, 256, 0, st>>>(LinvP, K - 1, Z, w);
+    for (int k = K - 1; k > 0; k--) k_fix_step<true><<<k, 256, 0, st>>>(Lstrips, LinvP, k, Z, w);
   }
   return hipGetLastError();
 }

@@ -62,6 +62,9 @@ __device__ __forceinline__ void gemm_staged_f64(const double* __restrict__ Lk,
   constexpr int LPW_HI = (CPS + NW - 1) / NW, LPW_LO = CPS / NW;
   double(*ring)[CPS * 128] = reinterpret_cast<double(*)[CPS * 128]>(ring_base);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x % 64;
+  // (lets the compiler resolve which chunks a wave copies: no branches in
+  // the loop)
+  __builtin_assume(wave >= 0 && wave < NW);
   const int wr = wave / WC, wc = wave % WC;
   const int nst = npairs / G;
   const bool hi = LPW_HI == LPW_LO || wave < CPS % NW;  // this wave copies LPW_HI chunks

@@ -1,7 +1,8 @@
-// Issue-rate measurement behind the FP32_REFINE solve's ceiling: throughput
-// of v_mfma_f32_16x16x4f32 when each MFMA is followed by NV independent
-// VALU instructions of one kind in the same wave (FP32 FMA, FP64 add, FP32
-// to FP64 conversion, FP32 add), with one or two waves per SIMD.  The
+// Issue-rate measurement behind the solves' ceilings: throughput of
+// v_mfma_f32_16x16x4f32 when each MFMA is followed by NV independent VALU
+// instructions of one kind in the same wave (FP32 FMA, FP64 add, FP32 to
+// FP64 conversion, FP32 add), and of a plain v_mfma_f64_16x16x4f64 stream,
+// with one or two waves per SIMD.  The
 // mixed-precision solve folds every FP32 chunk into its FP64 running sum
 // with one conversion and one FP64 add per accumulator element, i.e. two
 // such VALU instructions per MFMA; this program measures what that mix can
@@ -39,6 +40,23 @@ __global__ __launch_bounds__(512) void k_mix(float* out, int iters) {
   }
   const float fy = 1.0000001f;
   const double dy = 1.0000000001;
+  if (MODE == 5) {
+    // FP64 MFMAs only: eight independent 16 x 16 FP64 accumulators
+    typedef double d4v __attribute__((ext_vector_type(4)));
+    d4v e[8];
+    for (int i = 0; i < 8; i++) e[i] = (d4v){0, 0, 0, 0};
+    const double da = a, db = b;
+    for (int it = 0; it < iters; it++) {
+#pragma unroll
+      for (int t = 0; t < 8; t++)
+        asm volatile("v_mfma_f64_16x16x4_f64 %0, %1, %2, %0" : "+v"(e[t]) : "v"(da), "v"(db));
+    }
+    asm volatile("s_nop 7\n s_nop 7\n s_nop 7\n s_nop 7" ::: "memory");
+    double sum = 0;
+    for (int i = 0; i < 8; i++) sum += e[i][0] + e[i][1] + e[i][2] + e[i][3];
+    out[blockIdx.x * blockDim.x + threadIdx.x] = (float)sum;
+    return;
+  }
   for (int it = 0; it < iters; it++) {
 #pragma unroll
     for (int t = 0; t < 8; t++) {
@@ -63,6 +81,7 @@ __global__ __launch_bounds__(512) void k_mix(float* out, int iters) {
 static const char* kind(int mode) {
   switch (mode) {
     case 0: return "none";
+    case 5: return "(FP64 MFMA)";
     case 1: return "v_fma_f32";
     case 2: return "v_add_f64";
     case 3: return "v_cvt_f64_f32";
@@ -86,8 +105,9 @@ static void run(int threads, int grid, float* out, int iters) {
   float ms = 0;
   CHK(hipEventElapsedTime(&ms, e0, e1));
   const double mfma = (double)grid * (threads / 64) * iters * 8;
-  std::printf("valu %-14s per_mfma %d waves_per_simd %d: %.3f ms, %.1f TFLOP/s of FP32 MFMA\n",
-              kind(MODE), NV, threads / 256, ms, mfma * 2048 / (ms * 1e-3) / 1e12);
+  std::printf("valu %-14s per_mfma %d waves_per_simd %d: %.3f ms, %.1f TFLOP/s of %s MFMA\n",
+              kind(MODE), NV, threads / 256, ms, mfma * 2048 / (ms * 1e-3) / 1e12,
+              MODE == 5 ? "FP64" : "FP32");
   CHK(hipEventDestroy(e0));
   CHK(hipEventDestroy(e1));
 }
@@ -100,6 +120,7 @@ int main() {
   float* out = nullptr;
   CHK(hipMalloc(&out, sizeof(float) * (size_t)grid * 512));
   for (int threads : {256, 512}) {
+    run<5, 0>(threads, grid, out, iters / 2);
     run<0, 0>(threads, grid, out, iters);
     run<1, 1>(threads, grid, out, iters);
     run<1, 2>(threads, grid, out, iters);
