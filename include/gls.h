@@ -50,16 +50,17 @@ typedef struct gls_handle_s* gls_handle;
  *   phenotype, max-norm) against the FP64 definition: ~3e-14 at the
  *   workloads' conditioning; the target is 1e-10.
  * GLS_FP32_REFINE: the off-diagonal products of the triangular solve in
- *   FP32 matrix cores (FP32 accumulation over 16 k-values, FP64 running
- *   sum), everything else in FP64, and one FP64 refinement step of the
+ *   FP32 matrix cores (FP32 sums over 32 k-values, each two FP32 chains
+ *   of 16 added in FP32, then an FP64 running sum), everything else in
+ *   FP64, and one FP64 refinement step of the
  *   normal equations per problem.  Not part of the paper, whose routines
  *   are FP64 only.  The FP32-rounded operands leave an error that grows
  *   with kappa(L) = sqrt(kappa(M)) and that the refinement cannot remove
  *   where it enters X_R^T M^-1 X_R, so the stated bound on the max relative
  *   error of b_i depends on the 2-norm condition number of M:
- *       kappa(M) <= 10     1e-8   (measured 3.3e-9 at kappa 3.6)
- *       kappa(M) <= 60     3e-8   (measured 1.9e-8 at kappa 51)
- *       kappa(M) <= 250    6e-8   (measured 3.9e-8 at kappa 209)
+ *       kappa(M) <= 10     1e-8   (measured 3.7e-9 at kappa 3.6)
+ *       kappa(M) <= 60     3e-8   (measured 2.4e-8 at kappa 51)
+ *       kappa(M) <= 250    6e-8   (measured 4.1e-8 at kappa 209)
  *       kappa(M) <= 1000   1e-7   (measured 4.9e-8 at kappa 799)
  *   (1,000 problems at n = 1,200 each, M = h Phi + (1-h) I + 1e-3 I).  No
  *   bound is stated beyond kappa(M) = 1000: use GLS_FP64 there. */

@@ -15,12 +15,6 @@ constexpr int AS_GROUP_COLS = 64;  // columns per work-group of the assembly and
 #define GLS_TRSM_DEPTH 4
 #endif
 constexpr int TRSM_DEPTH = GLS_TRSM_DEPTH;  // k-step pairs in flight in the solve's GEMM loop
-#ifndef GLS_FP32_CHUNK_QUADS
-#define GLS_FP32_CHUNK_QUADS 1
-#endif
-// FP32_REFINE: k-step quads (4 k-steps each) accumulated in FP32 before the
-// running FP64 sum is updated; 8 = one whole 128-row block
-constexpr int FP32_CHUNK_QUADS = GLS_FP32_CHUNK_QUADS;
 
 // One block of columns of one cohort for the triangular-solve kernel.
 struct JobDesc {

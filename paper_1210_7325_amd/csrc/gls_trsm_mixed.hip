@@ -22,10 +22,52 @@ __host__ __device__ inline bool mixed_last_block_split(int64_t n, int K, int RW)
 // copies of stage st+1 and for its LDS reads, passes the barrier (stage st+1
 // visible to all, stage st read by all), refills stage st's slot with stage
 // st+S, reads the first quad of stage st+1 and runs the second quad of
-// stage st.  FP32 accumulation over one quad, then the FP64 running sum, as
-// in the register-ring form.
+// stage st.  The two quads of a stage form one chunk of the FP64 running
+// sum (quad_chain_fold), as two consecutive quads do in the register-ring form.
 template <int C, int G>
 constexpr int staged_ring_floats(int S) { return S * G * (NB / 16 + C / 16) * 256; }
+
+// One k-step quad of FP32 MFMAs for every tile of a wave: c = sum over the
+// quad's four k-steps (a fresh chain from zero).
+template <int RT, int CT>
+__device__ __forceinline__ void quad_chain(const f4 (&a)[RT], const f4 (&b)[CT], f4 (&c)[RT][CT]) {
+#pragma unroll
+  for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+    for (int ct = 0; ct < CT; ct++) {
+      f4 x = MFMA32(a[rt].x, b[ct].x, ((f4){0, 0, 0, 0}));
+      x = MFMA32(a[rt].y, b[ct].y, x);
+      x = MFMA32(a[rt].z, b[ct].z, x);
+      c[rt][ct] = MFMA32(a[rt].w, b[ct].w, x);
+    }
+}
+
+// The FP64 running sum of the mixed solve takes the products in chunks of
+// two k-step quads (32 k-values): c0 holds the first quad's FP32 chains
+// (quad_chain), this runs the second quad's chains, adds the two in FP32 and
+// adds that sum into the FP64 accumulator.  One tile row at a time, so that
+// only one row of second-quad chains is live.  Every form of the solve
+// (register ring, LDS staging, last-block kernel) forms the same chunks in
+// the same order, so their results are the same bits.
+template <int RT, int CT>
+__device__ __forceinline__ void quad_chain_fold(const f4 (&a)[RT], const f4 (&b)[CT], const f4 (&c0)[RT][CT],
+                                                d4 (&acc)[RT][CT]) {
+#pragma unroll
+  for (int rt = 0; rt < RT; rt++) {
+    f4 x[CT];
+#pragma unroll
+    for (int ct = 0; ct < CT; ct++) {
+      x[ct] = MFMA32(a[rt].x, b[ct].x, ((f4){0, 0, 0, 0}));
+      x[ct] = MFMA32(a[rt].y, b[ct].y, x[ct]);
+      x[ct] = MFMA32(a[rt].z, b[ct].z, x[ct]);
+      x[ct] = MFMA32(a[rt].w, b[ct].w, x[ct]);
+    }
+#pragma unroll
+    for (int ct = 0; ct < CT; ct++)
+#pragma unroll
+      for (int i = 0; i < 4; i++) acc[rt][ct][i] += (double)(c0[rt][ct][i] + x[ct][i]);
+  }
+}
 
 template <int C, int WR, int WC, int G, int S>
 __device__ __forceinline__ void gemm_staged(const float* __restrict__ Lk, const float* __restrict__ W32slab,
@@ -39,6 +81,7 @@ __device__ __forceinline__ void gemm_staged(const float* __restrict__ Lk, const 
   constexpr int LPW_HI = (CPS + NW - 1) / NW, LPW_LO = CPS / NW;
   float(*ring)[CPS * 256] = reinterpret_cast<float(*)[CPS * 256]>(ring_base);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x % 64;
+  __builtin_assume(wave >= 0 && wave < NW);
   const int wr = wave / WC, wc = wave % WC;
   const int nst = nq / G;
   const bool hi = LPW_HI == LPW_LO || wave < CPS % NW;  // this wave copies LPW_HI chunks
@@ -66,22 +109,7 @@ __device__ __forceinline__ void gemm_staged(const float* __restrict__ Lk, const 
     for (int ct = 0; ct < CT; ct++)
       b[ct] = *reinterpret_cast<const f4*>(slot + (CL + g * CTS + wc * CT + ct) * 256 + lane * 4);
   };
-  // each tile's quad is a fresh FP32 chain (started from zero) folded into
-  // the FP64 sum as soon as it is done: the fold of one tile has no
-  // dependence on the next tile's MFMAs, so the two overlap
-  auto mfma_quad = [&](const f4 (&a)[RT], const f4 (&b)[CT]) {
-#pragma unroll
-    for (int rt = 0; rt < RT; rt++)
-#pragma unroll
-      for (int ct = 0; ct < CT; ct++) {
-        f4 c = MFMA32(a[rt].x, b[ct].x, ((f4){0, 0, 0, 0}));
-        c = MFMA32(a[rt].y, b[ct].y, c);
-        c = MFMA32(a[rt].z, b[ct].z, c);
-        c = MFMA32(a[rt].w, b[ct].w, c);
-#pragma unroll
-        for (int i = 0; i < 4; i++) acc[rt][ct][i] += (double)c[i];
-      }
-  };
+  // the two quads of a stage form one chunk of the FP64 sum
   // all S slots filled, stage 0 visible
 #pragma unroll
   for (int st = 0; st < S; st++) issue(st);
@@ -91,6 +119,7 @@ __device__ __forceinline__ void gemm_staged(const float* __restrict__ Lk, const 
     wait_vm_lgkm0<(S - 1) * LPW_LO>();
   barrier_only();
   f4 a0[RT], b0[CT], a1[RT], b1[CT];
+  f4 c0[RT][CT];
   read_quad(0, 0, a0, b0);
   for (int st = 0; st < nst; st++) {
     // the first quad's reads, issued a quad of MFMAs ago, have landed; waiting
@@ -100,7 +129,7 @@ __device__ __forceinline__ void gemm_staged(const float* __restrict__ Lk, const 
     // the reads go out before the MFMAs that hide them, and the MFMAs before
     // the wait and the barrier
     __builtin_amdgcn_sched_barrier(0);
-    mfma_quad(a0, b0);
+    quad_chain<RT, CT>(a0, b0, c0);
     __builtin_amdgcn_sched_barrier(0);
     // stage st+1 is in LDS for every wave; every wave has read all of stage st
     if (hi)
@@ -111,7 +140,7 @@ __device__ __forceinline__ void gemm_staged(const float* __restrict__ Lk, const 
     issue(st + S);
     read_quad(st + 1, 0, a0, b0);  // (past the last stage: a clamped copy, unused)
     __builtin_amdgcn_sched_barrier(0);
-    mfma_quad(a1, b1);
+    quad_chain_fold<RT, CT>(a1, b1, c0, acc);
     asm volatile("" ::: "memory");
   }
   // the ring shares its LDS with the right-hand side staged next: the tail
@@ -122,9 +151,9 @@ __device__ __forceinline__ void gemm_staged(const float* __restrict__ Lk, const 
 
 // Mixed-precision blocked lower solve W = L^{-1}(X - 1 s^T): as k_trsm, but
 // each off-diagonal product L_kj W_j uses FP32-rounded operands on FP32 MFMA
-// (v_mfma_f32_16x16x4f32) with FP32 accumulation over one chunk of CHQ
-// k-step quads (4 k-steps each; CHQ = NB/16 is one whole diagonal block),
-// and the chunk is added into an FP64 running accumulator.  The diagonal
+// (v_mfma_f32_16x16x4f32) with FP32 accumulation over one chunk of two
+// k-step quads (4 k-steps each), and the chunk is added into an FP64
+// running accumulator (quad_chain_fold).  The diagonal
 // step inv(L_kk) R_k stays FP64.  Both W (FP64, for the assembly) and an
 // FP32 copy (quad layout, for later trailing products) are stored.
 // The FP32 output layout is lane l, element i -> row 4(l/16) + i.
@@ -132,14 +161,14 @@ __device__ __forceinline__ void gemm_staged(const float* __restrict__ Lk, const 
 // per wave (each wave loads its own tiles); S > 0, stages of G quads copied
 // through S LDS slots (gemm_staged), which lets one work-group take 128
 // columns (a 32 x 64 tile per wave) and halves the L traffic per column.
-template <int C, int WR, int WC, int D, int CHQ, int G = 1, int S = 0>
+template <int C, int WR, int WC, int D, int G = 1, int S = 0>
 __global__ __launch_bounds__(64 * WR * WC) void k_trsm_mixed(const JobTable tab) {
   constexpr int RW = NB / WR, RT = RW / 16;
   constexpr int CW = C / WC, CT = CW / 16;
   constexpr int CTS = C / 16;
   constexpr int NQB = NB / 16;  // k-step quads per row block
-  static_assert(NQB % CHQ == 0 && (CHQ % D == 0 || D % CHQ == 0), "chunking");
-  static_assert(S == 0 || (CHQ == 1 && NQB % G == 0 && S >= 2), "staging");
+  static_assert(D % 2 == 0, "quads are folded in pairs within a ring group");
+  static_assert(S == 0 || (G == 2 && NQB % G == 0 && S >= 2), "staging: a stage is a pair of quads");
   // R_k for the diagonal step; with staged operands the same LDS holds the
   // stage ring during the GEMM
   constexpr int RL_DOUBLES = NB * C > staged_ring_floats<C, G>(S) / 2 ? NB * C : staged_ring_floats<C, G>(S) / 2;
@@ -203,23 +232,21 @@ __global__ __launch_bounds__(64 * WR * WC) void k_trsm_mixed(const JobTable tab)
     }
 
     d4 acc[RT][CT];
-    f4 c32[RT][CT];
 #pragma unroll
     for (int a = 0; a < RT; a++)
 #pragma unroll
-      for (int b = 0; b < CT; b++) {
-        acc[a][b] = (d4){0, 0, 0, 0};
-        c32[a][b] = (f4){0, 0, 0, 0};
-      }
+      for (int b = 0; b < CT; b++) acc[a][b] = (d4){0, 0, 0, 0};
 
     const int nq = k * NQB;
     if constexpr (S > 0) {
       if (nq > 0) gemm_staged<C, WR, WC, G, S>(L32 + strip_offset(k), W32slab, nq, reinterpret_cast<float*>(Rl), acc);
     } else if (nq > 0) {
-      // register ring: D quads in flight, each wave loading its own tiles
+      // register ring: D quads in flight, each wave loading its own tiles;
+      // quads 2i and 2i+1 of the ring form one chunk (quad_chain_fold)
       const float* __restrict__ Ls = L32 + strip_offset(k) + (size_t)(wr * RT) * 256 + lane * 4;
       const float* __restrict__ Wb = W32slab + (size_t)(wc * CT) * 256 + lane * 4;
       f4 a[D][RT], b[D][CT];
+      f4 c0[RT][CT];
 #pragma unroll
       for (int s = 0; s < D; s++) {
 #pragma unroll
@@ -232,15 +259,10 @@ __global__ __launch_bounds__(64 * WR * WC) void k_trsm_mixed(const JobTable tab)
       for (int q0 = 0; q0 < nq; q0 += D) {
 #pragma unroll
         for (int s = 0; s < D; s++) {
-#pragma unroll
-          for (int rt = 0; rt < RT; rt++)
-#pragma unroll
-            for (int ct = 0; ct < CT; ct++) {
-              c32[rt][ct] = MFMA32(a[s][rt].x, b[s][ct].x, c32[rt][ct]);
-              c32[rt][ct] = MFMA32(a[s][rt].y, b[s][ct].y, c32[rt][ct]);
-              c32[rt][ct] = MFMA32(a[s][rt].z, b[s][ct].z, c32[rt][ct]);
-              c32[rt][ct] = MFMA32(a[s][rt].w, b[s][ct].w, c32[rt][ct]);
-            }
+          if (s % 2 == 0)
+            quad_chain<RT, CT>(a[s], b[s], c0);
+          else
+            quad_chain_fold<RT, CT>(a[s], b[s], c0, acc);
           int nx = q0 + s + D;
           nx = nx < nq ? nx : nq - 1;
 #pragma unroll
@@ -250,27 +272,6 @@ __global__ __launch_bounds__(64 * WR * WC) void k_trsm_mixed(const JobTable tab)
           for (int ct = 0; ct < CT; ct++)
             b[s][ct] = *reinterpret_cast<const f4*>(Wb + ((size_t)nx * CTS + ct) * 256);
           asm volatile("" ::: "memory");
-          if (CHQ <= D && (s + 1) % CHQ == 0) {
-            // end of an FP32 chunk: fold into the FP64 running sum
-#pragma unroll
-            for (int rt = 0; rt < RT; rt++)
-#pragma unroll
-              for (int ct = 0; ct < CT; ct++) {
-#pragma unroll
-                for (int i = 0; i < 4; i++) acc[rt][ct][i] += (double)c32[rt][ct][i];
-                c32[rt][ct] = (f4){0, 0, 0, 0};
-              }
-          }
-        }
-        if (CHQ > D && (q0 + D) % CHQ == 0) {
-#pragma unroll
-          for (int rt = 0; rt < RT; rt++)
-#pragma unroll
-            for (int ct = 0; ct < CT; ct++) {
-#pragma unroll
-              for (int i = 0; i < 4; i++) acc[rt][ct][i] += (double)c32[rt][ct][i];
-              c32[rt][ct] = (f4){0, 0, 0, 0};
-            }
         }
       }
     }
@@ -346,13 +347,13 @@ __global__ __launch_bounds__(64 * WR * WC) void k_trsm_mixed(const JobTable tab)
 // over its quarter of the quads), the FP64 partial sums meet in LDS in a
 // fixed order, then the FP64 diagonal step and both stores run as in
 // k_trsm_mixed (rows beyond the first tile give W = 0, as padding must).
-template <int C, int WR, int WC, int D, int CHQ>
+template <int C, int WR, int WC, int D>
 __global__ __launch_bounds__(64 * WR * WC) void k_trsm_mixed_last(const JobTable tab) {
   constexpr int RW = NB / WR, RT = RW / 16;
   constexpr int CW = C / WC, CT = CW / 16;
   constexpr int CTS = C / 16;
   constexpr int NQB = NB / 16;
-  static_assert(CHQ == 1 || D % CHQ == 0, "chunks within one stage group");
+  static_assert(D % 2 == 0, "quads are folded in pairs within a ring group");
   __shared__ __attribute__((aligned(16))) double Rl[NB * C];
 
   int jb = 0;
@@ -385,20 +386,17 @@ __global__ __launch_bounds__(64 * WR * WC) void k_trsm_mixed_last(const JobTable
       }
     }
   d4 acc[RT][CT];
-  f4 c32[RT][CT];
 #pragma unroll
   for (int a = 0; a < RT; a++)
 #pragma unroll
-    for (int b = 0; b < CT; b++) {
-      acc[a][b] = (d4){0, 0, 0, 0};
-      c32[a][b] = (f4){0, 0, 0, 0};
-    }
+    for (int b = 0; b < CT; b++) acc[a][b] = (d4){0, 0, 0, 0};
   const float* __restrict__ Ls = J.Lstrips32 + strip_offset(k) + lane * 4;  // row tile 0
   const float* __restrict__ Wb = W32slab + (size_t)(wc * CT) * 256 + lane * 4;
   const int ng = k * NQB / D;  // groups of D quads
   const int q0b = ng * wr / WR * D, q1b = ng * (wr + 1) / WR * D;
   if (q1b > q0b) {
     f4 a[D][RT], b[D][CT];
+    f4 c0[RT][CT];
 #pragma unroll
     for (int s = 0; s < D; s++) {
 #pragma unroll
@@ -412,15 +410,10 @@ __global__ __launch_bounds__(64 * WR * WC) void k_trsm_mixed_last(const JobTable
     for (int q0 = q0b; q0 < q1b; q0 += D) {
 #pragma unroll
       for (int s = 0; s < D; s++) {
-#pragma unroll
-        for (int rt = 0; rt < RT; rt++)
-#pragma unroll
-          for (int ct = 0; ct < CT; ct++) {
-            c32[rt][ct] = MFMA32(a[s][rt].x, b[s][ct].x, c32[rt][ct]);
-            c32[rt][ct] = MFMA32(a[s][rt].y, b[s][ct].y, c32[rt][ct]);
-            c32[rt][ct] = MFMA32(a[s][rt].z, b[s][ct].z, c32[rt][ct]);
-            c32[rt][ct] = MFMA32(a[s][rt].w, b[s][ct].w, c32[rt][ct]);
-          }
+        if (s % 2 == 0)
+          quad_chain<RT, CT>(a[s], b[s], c0);
+        else
+          quad_chain_fold<RT, CT>(a[s], b[s], c0, acc);
         int nx = q0 + s + D;
         nx = nx < q1b ? nx : q1b - 1;
 #pragma unroll
@@ -430,17 +423,6 @@ __global__ __launch_bounds__(64 * WR * WC) void k_trsm_mixed_last(const JobTable
         for (int ct = 0; ct < CT; ct++)
           b[s][ct] = *reinterpret_cast<const f4*>(Wb + ((size_t)nx * CTS + ct) * 256);
         asm volatile("" ::: "memory");
-        if ((s + 1) % CHQ == 0) {
-          // end of an FP32 chunk: fold into the FP64 running sum
-#pragma unroll
-          for (int rt = 0; rt < RT; rt++)
-#pragma unroll
-            for (int ct = 0; ct < CT; ct++) {
-#pragma unroll
-              for (int i = 0; i < 4; i++) acc[rt][ct][i] += (double)c32[rt][ct][i];
-              c32[rt][ct] = (f4){0, 0, 0, 0};
-            }
-        }
       }
     }
   }
@@ -516,16 +498,16 @@ hipError_t launch_trsm_mixed(const JobTable& tab, int64_t nslabs, int C, hipStre
   for (int i = 0; i < tab.njobs; i++) last = last || mixed_last_block_split(tab.j[i].n, tab.j[i].K, NB / 4);
   switch (C) {
     case 32:
-      k_trsm_mixed<32, 4, 2, 4, FP32_CHUNK_QUADS><<<(unsigned)nslabs, 512, 0, st>>>(tab);
-      if (last) k_trsm_mixed_last<32, 4, 2, 4, FP32_CHUNK_QUADS><<<(unsigned)nslabs, 512, 0, st>>>(tab);
+      k_trsm_mixed<32, 4, 2, 4><<<(unsigned)nslabs, 512, 0, st>>>(tab);
+      if (last) k_trsm_mixed_last<32, 4, 2, 4><<<(unsigned)nslabs, 512, 0, st>>>(tab);
       break;
     case 64:
-      k_trsm_mixed<64, 4, 2, 4, FP32_CHUNK_QUADS, 2, 4><<<(unsigned)nslabs, 512, 0, st>>>(tab);
-      if (last) k_trsm_mixed_last<64, 4, 2, 4, FP32_CHUNK_QUADS><<<(unsigned)nslabs, 512, 0, st>>>(tab);
+      k_trsm_mixed<64, 4, 2, 4, 2, 4><<<(unsigned)nslabs, 512, 0, st>>>(tab);
+      if (last) k_trsm_mixed_last<64, 4, 2, 4><<<(unsigned)nslabs, 512, 0, st>>>(tab);
       break;
     case 128:
-      k_trsm_mixed<128, 4, 2, 4, FP32_CHUNK_QUADS, 2, 4><<<(unsigned)nslabs, 512, 0, st>>>(tab);
-      if (last) k_trsm_mixed_last<128, 4, 2, 2, FP32_CHUNK_QUADS><<<(unsigned)nslabs, 512, 0, st>>>(tab);
+      k_trsm_mixed<128, 4, 2, 4, 2, 4><<<(unsigned)nslabs, 512, 0, st>>>(tab);
+      if (last) k_trsm_mixed_last<128, 4, 2, 2><<<(unsigned)nslabs, 512, 0, st>>>(tab);
       break;
     default: return hipErrorInvalidValue;
   }
