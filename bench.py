@@ -943,8 +943,8 @@ def main():
         "bound": "mfma", "achieved": round(head["trsm_tflops"], 3), "peak": head["peak"],
         "unit": "TFLOP/s", "frac": round(head["trsm_tflops"] / head["peak"], 4),
         "traffic": measured_traffic(batch, args.slab_cols, forms[0]),
-        "kernel": "k_trsm (blocked lower solve, " + ("FP64 MFMA)" if forms[0] == "fp64" else
-                                                      "FP32 MFMA products + FP64 diagonal)"),
+        "kernel": ("k_trsm_pair (blocked lower solve, row blocks in pairs, FP64 MFMA)" if forms[0] == "fp64"
+                   else "k_trsm_mixed (blocked lower solve, FP32 MFMA products + FP64 diagonal)"),
         "launches": head["trsm_launches"], "avg_launch_ms": round(head["trsm_avg_ms"], 4),
         "flops_per_launch": head["flops_per_launch"], "blocks_per_launch": batch,
         "step_tflops": round(head["step_tflops"], 3),
