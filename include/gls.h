@@ -212,7 +212,12 @@ int gls_whiten_block_f64(gls_handle h, int64_t ncols, const double* X, int64_t l
  * launches finish sooner in narrow slabs and full launches run best in wide
  * ones — except that 64 is kept when a 128-column slab of the launch's
  * largest cohort would take longer than the launch's 64-column slabs spread
- * over the compute units (launches mixing cohorts of different n).  Other
+ * over the compute units (launches mixing cohorts of different n).  With
+ * the automatic width, the work of a gls_solve_block call, or of a
+ * gls_solve_multi call whose items share one cohort, that needs more slabs
+ * than there are compute units goes out in rounds: one launch of the
+ * columns that give one slab per compute unit, then the rest at the width
+ * chosen for it (an item may be split between two launches).  Other
  * values return -2.  A performance knob only: every column is
  * whitened by the same sequence of operations whatever its slab, so results
  * are bitwise independent of it.  Items of one gls_solve_multi call must
@@ -333,8 +338,10 @@ int gls_writer_close(gls_file_writer w, int64_t* bytes, double* write_ms, double
 /* ---- several cohorts in one launch (serving) ----------------------------
  * One work item per block of problems of one handle.  All items are
  * whitened by one launch of the triangular-solve kernel and assembled and
- * solved by one more, on `stream` (not the handles' own streams; the
- * caller orders them).  Each item needs its own handle (or fork), because
+ * solved by one more (in rounds, as described under gls_set_slab_cols,
+ * when the items share one cohort and need more slabs than there are
+ * compute units; in launches of at most 16 items otherwise), on `stream`
+ * (not the handles' own streams; the caller orders them).  Each item needs its own handle (or fork), because
  * the item uses the handle's workspace.  Results equal gls_solve_block's
  * for the same item bit for bit.  The library records, per handle, the
  * stream of the last launch that used its workspace; growing the workspace

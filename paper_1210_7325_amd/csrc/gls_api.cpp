@@ -285,7 +285,7 @@ int slab_cols_for(const gls_work* items, int64_t count) {
 // handle th (none if th is NULL).  ws: the workspace of a single item, or
 // NULL for each item's own (grown here when too small).
 int launch_items(const gls_work* items, int64_t count, hipStream_t st, gls_handle th,
-                 const Workspace* ws = nullptr) {
+                 const Workspace* ws = nullptr, int C_set = 0) {
   if (!ws) {
     for (int64_t i = 0; i < count; i++) {
       int rc = ensure_workspace(items[i].h, items[i].nsnp * items[i].p_R);
@@ -294,7 +294,7 @@ int launch_items(const gls_work* items, int64_t count, hipStream_t st, gls_handl
   } else if (count != 1) {
     return GLS_E_UNSUPPORTED;
   }
-  const int C = slab_cols_for(items, count);
+  const int C = C_set ? C_set : slab_cols_for(items, count);
   const bool refine = items[0].h->c->prec == GLS_FP32_REFINE;
   JobTable tab;
   AsmTable at;
@@ -339,6 +339,66 @@ int launch_items(const gls_work* items, int64_t count, hipStream_t st, gls_handl
         if (int rc = workspace_used(items[i].h, st)) return rc;
   }
   return hip_code(e);
+}
+
+// Launch the work items of one call in rounds of at most one work-group per
+// compute unit.  A launch whose slabs outnumber the compute units runs a
+// second, partly empty round of whole slab walks (a walk takes as long
+// whatever runs beside it); here the columns that fill one round form one
+// launch and the rest the next, whose slab width is chosen for its own size
+// (a narrower slab walks its row blocks faster): at n = 10^4, 16,960
+// columns in 256 64-column slabs and then 36 16-column ones instead of 265
+// 64-column slabs.  An item can be split between two launches: they are
+// ordered on stream st, so both parts use the item's workspace in turn.
+// Items of several cohorts (whose slab walks differ in length, which one
+// launch balances by itself) and handles with a fixed width are launched as
+// they are, in groups of MAX_INLINE_JOBS.
+int launch_rounds(const gls_work* items, int64_t count, hipStream_t st, gls_handle th) {
+  bool split = items[0].h->C == 0;
+  for (int64_t i = 1; i < count; i++) split = split && items[i].h->c == items[0].h->c;
+  if (!split) {
+    for (int64_t a = 0; a < count; a += MAX_INLINE_JOBS) {
+      int rc = launch_items(items + a, std::min<int64_t>(count - a, MAX_INLINE_JOBS), st, th);
+      if (rc) return rc;
+    }
+    return GLS_OK;
+  }
+  std::vector<gls_work> rest(items, items + count);
+  const int64_t cus = items[0].h->c->cus;
+  const int64_t t = items[0].h->c->t;
+  size_t at = 0;
+  while (at < rest.size()) {
+    const int C = slab_cols_for(&rest[at], (int64_t)(rest.size() - at));
+    gls_work batch[MAX_INLINE_JOBS];
+    int nb = 0;
+    int64_t slabs = 0;
+    while (at < rest.size() && nb < MAX_INLINE_JOBS) {
+      gls_work& w = rest[at];
+      const int64_t s = (w.nsnp * w.p_R + C - 1) / C;
+      if (slabs + s <= cus) {
+        batch[nb++] = w;
+        slabs += s;
+        at++;
+        continue;
+      }
+      // the item's first problems fill the round; the rest stays for the next
+      const int64_t take = (cus - slabs) * C / w.p_R;
+      if (take > 0) {
+        gls_work a = w;
+        a.nsnp = take;
+        batch[nb++] = a;
+        w.nsnp -= take;
+        w.X_R += take * w.p_R * w.ldxr;
+        w.B += take * t * w.ldb;
+        w.info += take;
+      }
+      break;
+    }
+    if (nb == 0) return GLS_E_UNSUPPORTED;  // (a problem wider than a round: not reachable, p_R <= 16)
+    int rc = launch_items(batch, nb, st, th, nullptr, C);
+    if (rc) return rc;
+  }
+  return GLS_OK;
 }
 
 }  // namespace
@@ -552,7 +612,7 @@ int gls_solve_block(gls_handle h, int64_t nsnp, int64_t p_R, const int8_t* X_R, 
   if (rc) return rc;
   if (nsnp == 0) return GLS_OK;
   gls_work w{h, nsnp, p_R, X_R, ldxr, B, ldb, info};
-  return launch_items(&w, 1, h->stream, h);
+  return launch_rounds(&w, 1, h->stream, h);
 }
 
 int gls_solve_multi(const gls_work* items, int64_t count, void* stream) {
@@ -571,12 +631,7 @@ int gls_solve_multi(const gls_work* items, int64_t count, void* stream) {
     for (int64_t j = 0; j < i; j++)
       if (items[j].h == w.h) return -1;  // each item needs its own workspace
   }
-  for (int64_t a = 0; a < count; a += MAX_INLINE_JOBS) {
-    const int64_t b = std::min<int64_t>(count, a + MAX_INLINE_JOBS);
-    int rc = launch_items(items + a, b - a, st, items[a].h);
-    if (rc) return rc;
-  }
-  return GLS_OK;
+  return launch_rounds(items, count, st, items[0].h);
 }
 
 int gls_fork(gls_handle h, void* stream, gls_handle* out) {
@@ -864,7 +919,7 @@ int gls_solve_stream(gls_handle h, int64_t snp_begin, int64_t snp_end, int64_t b
     STREAM_CHK(hipStreamWaitEvent(h->stream, ev_in[sj], 0));
     if (j >= 2) STREAM_CHK(hipStreamWaitEvent(h->stream, ev_out[sj], 0));
     gls_work w{h, len, p_R, din[sj], n, dB[sj], p, dinfo[sj]};
-    rc = launch_items(&w, 1, h->stream, h);
+    rc = launch_rounds(&w, 1, h->stream, h);
     if (rc) {
       cleanup();
       return rc;

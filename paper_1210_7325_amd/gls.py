@@ -430,8 +430,9 @@ class Cohort:
 
 
 def solve_multi(items, stream=None):
-    """items: list of (Cohort, XR, p_R, B, info) solved in one launch per
-    kernel on `stream`."""
+    """items: list of (Cohort, XR, p_R, B, info) solved together on
+    `stream` (one launch per kernel, or rounds of launches for one cohort's
+    work beyond one work-group per compute unit)."""
     works = []
     for c, XR, p_R, B, info in items:
         # no layout copies here: the launch reads the caller's arrays as they are

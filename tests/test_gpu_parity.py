@@ -383,3 +383,49 @@ def test_workspace_regrowth_after_launch_on_another_stream(G):
     assert orc.relative_error(Ba.cpu().numpy(), ref[:200]).max() < 1e-10
     assert orc.relative_error(Bb.cpu().numpy(), ref).max() < 1e-10
     c.free()
+
+
+@pytest.mark.parametrize("prec,pR,t", [("fp64", 1, 1), ("fp64", 3, 2), ("fp32_refine", 1, 2)])
+def test_rounds_split_items_bitwise(G, prec, pR, t):
+    """One cohort's work beyond one round of work-groups (more 64-column
+    slabs than compute units) goes out as a launch that fills the round and
+    one for the rest at its own width, splitting an item between the two:
+    the same bits as the same items at one fixed width (one launch), and
+    within the oracle's bound on a sample of problems, the split item's
+    included."""
+    from paper_1210_7325_amd import gls
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    n = 300
+    per_item = (cus * 64 * 11 // 10) // 3 // pR   # problems per item: 1.1 rounds of 64-column slabs in all
+    m = 3 * per_item
+    say("rounds", prec, pR, t, "cus", cus, "problems", m)
+    w, M, XL, Y, XR = small_problem(n, pR=pR, m=m, t=t, seed=17 + pR)
+    dXR = to_dev(XR)
+    outs = {}
+    for C in (0, 64):
+        c = gls.Cohort(to_dev(M), precision=prec).whiten_fixed(to_dev(XL), to_dev(Y), intercept_col=0)
+        hs = [c] + [c.fork(torch.cuda.current_stream()) for _ in range(2)]
+        for h in hs:
+            h.set_slab_cols(C)
+        p = 3 + pR
+        B = torch.full((m, t, p), float("nan"), dtype=torch.float64, device="cuda")
+        info = torch.full((m,), -7, dtype=torch.int32, device="cuda")
+        items = [(hs[j], dXR[:, j * per_item * pR:(j + 1) * per_item * pR], pR,
+                  B[j * per_item:(j + 1) * per_item], info[j * per_item:(j + 1) * per_item]) for j in range(3)]
+        gls.solve_multi(items, stream=torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        outs[C] = (B.cpu().numpy(), info.cpu().numpy())
+        for h in hs[1:]:
+            h.free()
+        c.free()
+    assert np.all(outs[0][1] == 0) and np.all(outs[64][1] == 0)
+    assert np.array_equal(outs[0][0], outs[64][0])
+    # the third item is split between the two launches: sample around its split
+    split = 2 * per_item + (cus - 2 * ((per_item * pR + 63) // 64)) * 64 // pR
+    idx = np.unique(np.clip(np.array([0, per_item - 1, per_item, 2 * per_item, split - 2, split - 1, split,
+                                      split + 1, m - 1]), 0, m - 1))
+    XRs = np.concatenate([XR[:, i * pR:(i + 1) * pR] for i in idx], axis=1)
+    ref = orc.gls_sequence(M, XL, XRs, Y, pR)
+    err = orc.relative_error(outs[0][0][idx], ref)
+    say("max rel err", err.max())
+    assert err.max() < (1e-10 if prec == "fp64" else 1e-8)
