@@ -461,49 +461,57 @@ __device__ __forceinline__ void to_pair_layout(double* __restrict__ Rl, int wr_r
   }
 }
 
-// W_k = inv(L_kk) R_k for the wave's tiles (R_k in LDS, pair layout; the
-// k-steps past the wave's last row are zero in inv(L_kk) and skipped)
-template <int RT, int CT, int CTS>
-__device__ __forceinline__ void diag_step(const double* __restrict__ LinvP, int k, const double* __restrict__ Rl,
-                                          int wr_rows, int wc_tile, int lane, d4 (&w)[RT][CT]) {
+// The diagonal step of k_trsm_pair with the row tiles dealt for balance:
+// 16-row tile t of inv(L_kk) R_k needs the first 2(t+1) k-step pairs (the
+// rest of its row of inv(L_kk) is zero), so wave row wr takes tiles wr and
+// NB/16 - 1 - wr (NB/8 + 2 pairs for every wave row, against up to 2 NB/8
+// for wave row WR - 1 when it holds the last two tiles).  Same products in
+// the same order per element as diag_step.
+template <int CT, int CTS>
+__device__ __forceinline__ void diag_step_dealt(const double* __restrict__ LinvP, int k,
+                                                const double* __restrict__ Rl, int wr, int wc_tile, int lane,
+                                                d4 (&w)[2][CT]) {
+  constexpr int NT = NB / 16;
+  const double* __restrict__ Li = LinvP + (size_t)k * NB * NB + lane * 2;
 #pragma unroll
-  for (int a = 0; a < RT; a++)
+  for (int h = 0; h < 2; h++) {
+    const int t = h == 0 ? wr : NT - 1 - wr;
 #pragma unroll
-    for (int b = 0; b < CT; b++) w[a][b] = (d4){0, 0, 0, 0};
-  const double* __restrict__ Li = LinvP + (size_t)k * NB * NB + (size_t)(wr_rows / 16) * 128 + lane * 2;
-  const int kp_end = (wr_rows + RT * 16) / 8;
-  for (int kp = 0; kp < kp_end; kp++) {
-    d2 a[RT], b[CT];
+    for (int b = 0; b < CT; b++) w[h][b] = (d4){0, 0, 0, 0};
+    const int kp_end = 2 * (t + 1);
+    for (int kp = 0; kp < kp_end; kp++) {
+      const d2 a = *reinterpret_cast<const d2*>(Li + ((size_t)kp * NT + t) * 128);
+      d2 b[CT];
 #pragma unroll
-    for (int rt = 0; rt < RT; rt++)
-      a[rt] = *reinterpret_cast<const d2*>(Li + ((size_t)kp * (NB / 16) + rt) * 128);
-#pragma unroll
-    for (int ct = 0; ct < CT; ct++)
-      b[ct] = *reinterpret_cast<const d2*>(&Rl[((size_t)kp * CTS + wc_tile + ct) * 128 + lane * 2]);
-#pragma unroll
-    for (int rt = 0; rt < RT; rt++)
+      for (int ct = 0; ct < CT; ct++)
+        b[ct] = *reinterpret_cast<const d2*>(&Rl[((size_t)kp * CTS + wc_tile + ct) * 128 + lane * 2]);
 #pragma unroll
       for (int ct = 0; ct < CT; ct++) {
-        w[rt][ct] = MFMA64(a[rt].x, b[ct].x, w[rt][ct]);
-        w[rt][ct] = MFMA64(a[rt].y, b[ct].y, w[rt][ct]);
+        w[h][ct] = MFMA64(a.x, b[ct].x, w[h][ct]);
+        w[h][ct] = MFMA64(a.y, b[ct].y, w[h][ct]);
       }
+    }
   }
 }
 
-// store the wave's W_k tiles to the slab (element i of the FP64 output is
-// k-step row0/4 + i at the same lane)
-template <int RT, int CT, int CTS>
-__device__ __forceinline__ void store_w(double* __restrict__ Wslab, int k, int wr_rows, int wc_tile, int lane,
-                                        const d4 (&w)[RT][CT]) {
+// The dealt tiles of diag_step_dealt: to the slab (rows k NB + 16 t) and,
+// when Wl is given, to LDS in the B-operand pair layout.
+template <int CT, int CTS>
+__device__ __forceinline__ void store_w_dealt(double* __restrict__ Wslab, double* __restrict__ Wl, int k, int wr,
+                                              int wc_tile, int lane, const d4 (&w)[2][CT]) {
+  constexpr int NT = NB / 16;
 #pragma unroll
-  for (int rt = 0; rt < RT; rt++) {
-    const int64_t ks0 = (int64_t)k * (NB / 4) + (wr_rows + rt * 16) / 4;
+  for (int h = 0; h < 2; h++) {
+    const int t = h == 0 ? wr : NT - 1 - wr;
+    const int64_t ks0 = (int64_t)k * (NB / 4) + 4 * t;
 #pragma unroll
     for (int ct = 0; ct < CT; ct++)
 #pragma unroll
-      for (int i = 0; i < 4; i += 2)
-        *reinterpret_cast<d2*>(Wslab + ((size_t)((ks0 + i) / 2) * CTS + wc_tile + ct) * 128 + lane * 2) =
-            (d2){w[rt][ct][i], w[rt][ct][i + 1]};
+      for (int i = 0; i < 4; i += 2) {
+        const d2 v = (d2){w[h][ct][i], w[h][ct][i + 1]};
+        *reinterpret_cast<d2*>(Wslab + ((size_t)((ks0 + i) / 2) * CTS + wc_tile + ct) * 128 + lane * 2) = v;
+        if (Wl) *reinterpret_cast<d2*>(&Wl[((size_t)((4 * t + i) / 2) * CTS + wc_tile + ct) * 128 + lane * 2]) = v;
+      }
   }
 }
 
@@ -516,6 +524,7 @@ __global__ __launch_bounds__(64 * PAIR_WR * PAIR_WC) void k_trsm_pair(const JobT
   constexpr int NPB = NB / 8;  // k-step pairs per row block
   constexpr int RING = S * 2 * (2 * (NB / 16) + CTS) * 128;
   constexpr int RL_DOUBLES = NB * C > RING ? NB * C : RING;
+  static_assert(RT == 2 && 2 * WR == NB / 16, "the diagonal steps deal two row tiles to each wave row");
   __shared__ __attribute__((aligned(16))) double Rl[RL_DOUBLES];
 
   int jb = 0;
@@ -548,22 +557,21 @@ __global__ __launch_bounds__(64 * PAIR_WR * PAIR_WC) void k_trsm_pair(const JobT
       gemm_staged_pair<C, WR, WC, S>(Lstrips + strip_offset(k), Lstrips + strip_offset(two ? k + 1 : k), Wslab,
                                      npairs, Rl, acc0, acc1);
 
-    // both blocks' right-hand sides; the second is consumed after the
-    // first block's diagonal step and the L_{k+1,k} W_k products, which hide
-    // its latency
     TIn xv0[RT][CT][4], xv1[RT][CT][4];
     load_rhs<RT, CT>(X, ldx, n, ncols, (int64_t)k * NB + wr_rows, col_base, lane, xv0);
-    if (two) load_rhs<RT, CT>(X, ldx, n, ncols, (int64_t)(k + 1) * NB + wr_rows, col_base, lane, xv1);
 
-    // block k: R_k to LDS, W_k = inv(L_kk) R_k, stored
+    // block k: R_k to LDS, W_k = inv(L_kk) R_k, stored (and, when block
+    // k+1 follows, put in LDS in place of R_k once every wave is done
+    // reading R_k)
     to_pair_layout<RT, CT, CTS>(Rl, wr_rows, wc_tile, lane, xv0, acc0, true);
     __syncthreads();
-    diag_step<RT, CT, CTS>(LinvP, k, Rl, wr_rows, wc_tile, lane, acc0);
-    store_w<RT, CT, CTS>(Wslab, k, wr_rows, wc_tile, lane, acc0);
+    diag_step_dealt<CT, CTS>(LinvP, k, Rl, wr, wc_tile, lane, acc0);
+    if (two) __syncthreads();
+    store_w_dealt<CT, CTS>(Wslab, two ? Rl : nullptr, k, wr, wc_tile, lane, acc0);
     if (two) {
-      // W_k replaces R_k in LDS once every wave is done reading R_k
-      __syncthreads();
-      to_pair_layout<RT, CT, CTS>(Rl, wr_rows, wc_tile, lane, xv0, acc0, false);
+      // block k+1's right-hand side, consumed after the L_{k+1,k} W_k
+      // products, which hide its latency
+      load_rhs<RT, CT>(X, ldx, n, ncols, (int64_t)(k + 1) * NB + wr_rows, col_base, lane, xv1);
       __syncthreads();
       // acc_{k+1} += L_{k+1,k} W_k: the last NPB pairs of strip k+1, a
       // register ring of D pairs
@@ -603,8 +611,8 @@ __global__ __launch_bounds__(64 * PAIR_WR * PAIR_WC) void k_trsm_pair(const JobT
       __syncthreads();
       to_pair_layout<RT, CT, CTS>(Rl, wr_rows, wc_tile, lane, xv1, acc1, true);
       __syncthreads();
-      diag_step<RT, CT, CTS>(LinvP, k + 1, Rl, wr_rows, wc_tile, lane, acc1);
-      store_w<RT, CT, CTS>(Wslab, k + 1, wr_rows, wc_tile, lane, acc1);
+      diag_step_dealt<CT, CTS>(LinvP, k + 1, Rl, wr, wc_tile, lane, acc1);
+      store_w_dealt<CT, CTS>(Wslab, nullptr, k + 1, wr, wc_tile, lane, acc1);
     }
     // the W stores are visible to the work-group's next copies, and every
     // wave is done reading Rl before the next stage ring overwrites it
