@@ -26,34 +26,57 @@ __global__ void k_pack_fixed(const double* __restrict__ XL, int64_t ldx, const d
   F[idx] = v;
 }
 
-// Unpack a 128 x 128 block stored in the fragment pair layout into T[row][col].
+// Unpack a 128 x 128 block stored in the fragment pair layout into T[row][col]
+// (256 threads).  Pair q of the block (16 bytes: k-steps 2 kp and 2 kp + 1 of
+// lane ln of row tile rt) goes to two entries of T.  Each thread issues its
+// loads in batches of 16 before storing any, so that the batch's latencies
+// overlap.
 __device__ __forceinline__ void stage_block(double (*T)[NB + 1], const double* __restrict__ blk) {
-  for (int d = threadIdx.x; d < NB * NB; d += blockDim.x) {
-    const int kk = d & 1, ln = (d >> 1) & 63, rt = (d >> 7) % (NB / 16), kp = (d >> 7) / (NB / 16);
-    T[rt * 16 + ln % 16][(2 * kp + kk) * 4 + ln / 16] = blk[d];
+  constexpr int PAIRS = NB * NB / 2, PER = PAIRS / 256, BATCH = 16;
+  static_assert(PER % BATCH == 0, "whole batches");
+  const d2* __restrict__ src = reinterpret_cast<const d2*>(blk);
+#pragma unroll
+  for (int b0 = 0; b0 < PER; b0 += BATCH) {
+    d2 v[BATCH];
+#pragma unroll
+    for (int i = 0; i < BATCH; i++) v[i] = src[threadIdx.x + 256 * (b0 + i)];
+#pragma unroll
+    for (int i = 0; i < BATCH; i++) {
+      const int q = threadIdx.x + 256 * (b0 + i);
+      const int ln = q & 63, rt = (q >> 6) % (NB / 16), kp = (q >> 6) / (NB / 16);
+      T[rt * 16 + ln % 16][(2 * kp) * 4 + ln / 16] = v[i].x;
+      T[rt * 16 + ln % 16][(2 * kp + 1) * 4 + ln / 16] = v[i].y;
+    }
   }
 }
 
 constexpr int FIX_COLS_PER_THREAD = (MAXP + MAXT + 1) / 2;
+constexpr int FIX_LD = MAXP + MAXT;  // row stride of a staged block of F
 
-// acc[ci] = sum_b op(T)[a][b] * F[(r0 + b) * w + c] over the thread's columns
+// Rows r0 .. r0 + NB - 1 of F (row-major, w columns: one contiguous run)
+// into Fs[row][col].
+__device__ __forceinline__ void stage_rows(double (*Fs)[FIX_LD], const double* __restrict__ F, int64_t r0,
+                                           int w) {
+  const double* __restrict__ src = F + r0 * w;
+  for (int d = threadIdx.x; d < NB * w; d += blockDim.x) Fs[d / w][d % w] = src[d];
+}
+
+// acc[ci] = sum_b op(T)[a][b] * Fs[b][c] over the thread's columns
 // c = half + 2 ci, with op(T) = T (lower) or T^T (upper) and b restricted to
-// the nonzero triangle when `tri` is set.
+// the nonzero triangle when `tri` is set.  Both operands are in LDS.
 template <bool UPPER>
-__device__ __forceinline__ void fix_product(const double (*T)[NB + 1], const double* __restrict__ F,
-                                            int64_t r0, int w, int a, int half, bool tri,
-                                            double (&acc)[FIX_COLS_PER_THREAD]) {
+__device__ __forceinline__ void fix_product(const double (*T)[NB + 1], const double (*Fs)[FIX_LD], int w, int a,
+                                            int half, bool tri, double (&acc)[FIX_COLS_PER_THREAD]) {
 #pragma unroll
   for (int ci = 0; ci < FIX_COLS_PER_THREAD; ci++) acc[ci] = 0.0;
   const int b0 = (tri && UPPER) ? a : 0;
   const int b1 = (tri && !UPPER) ? a + 1 : NB;
   for (int b = b0; b < b1; b++) {
     const double tv = UPPER ? T[b][a] : T[a][b];
-    const double* __restrict__ f = F + (r0 + b) * w;
 #pragma unroll
     for (int ci = 0; ci < FIX_COLS_PER_THREAD; ci++) {
       const int c = half + 2 * ci;
-      if (c < w) acc[ci] += tv * f[c];
+      if (c < w) acc[ci] += tv * Fs[b][c];
     }
   }
 }
@@ -62,12 +85,13 @@ template <bool UPPER>
 __global__ __launch_bounds__(256) void k_fix_diag(const double* __restrict__ LinvP, int k,
                                                   double* __restrict__ F, int w) {
   __shared__ double T[NB][NB + 1];
+  __shared__ double Fs[NB][FIX_LD];
   stage_block(T, LinvP + (size_t)k * NB * NB);
+  stage_rows(Fs, F, (int64_t)k * NB, w);
   __syncthreads();
   const int a = threadIdx.x % NB, half = threadIdx.x / NB;
   double acc[FIX_COLS_PER_THREAD];
-  fix_product<UPPER>(T, F, (int64_t)k * NB, w, a, half, true, acc);
-  __syncthreads();  // every read of block k happens before it is overwritten
+  fix_product<UPPER>(T, Fs, w, a, half, true, acc);
 #pragma unroll
   for (int ci = 0; ci < FIX_COLS_PER_THREAD; ci++) {
     const int c = half + 2 * ci;
@@ -78,36 +102,46 @@ __global__ __launch_bounds__(256) void k_fix_diag(const double* __restrict__ Lin
 // One step of the solve in a single launch: every work-group updates its
 // block j with block k (lower: F_j -= L_jk F_k, j > k; upper:
 // Z_j -= L_kj^T Z_k, j < k; the 128 x 128 block of L staged in LDS from its
-// contiguous packed form), and the one whose block is the
-// next to be finished (j = k + 1 for the lower solve, j = k - 1 for the
-// upper one) then applies that block's diagonal step (as k_fix_diag), so
-// that the next launch can use it.  K - 1 launches instead of 2K - 1.
+// contiguous packed form, block k of F beside it), and the one whose block
+// is the next to be finished (j = k + 1 for the lower solve, j = k - 1 for
+// the upper one) then applies that block's diagonal step (as k_fix_diag),
+// so that the next launch can use it.  K - 1 launches instead of 2K - 1.
 template <bool UPPER>
 __global__ __launch_bounds__(256) void k_fix_step(const double* __restrict__ Lstrips,
                                                   const double* __restrict__ LinvP, int k,
                                                   double* __restrict__ F, int w) {
   __shared__ double T[NB][NB + 1];
+  __shared__ double Fs[NB][FIX_LD];
   const int j = UPPER ? (int)blockIdx.x : k + 1 + (int)blockIdx.x;
   const double* blk = UPPER ? Lstrips + strip_offset(k) + (size_t)j * NB * NB
                             : Lstrips + strip_offset(j) + (size_t)k * NB * NB;
   stage_block(T, blk);
+  stage_rows(Fs, F, (int64_t)k * NB, w);
   __syncthreads();
   const int a = threadIdx.x % NB, half = threadIdx.x / NB;
-  double acc[FIX_COLS_PER_THREAD];
-  fix_product<UPPER>(T, F, (int64_t)k * NB, w, a, half, false, acc);
+  double acc[FIX_COLS_PER_THREAD], v[FIX_COLS_PER_THREAD];
+  fix_product<UPPER>(T, Fs, w, a, half, false, acc);
 #pragma unroll
   for (int ci = 0; ci < FIX_COLS_PER_THREAD; ci++) {
     const int c = half + 2 * ci;
-    if (c < w) F[((int64_t)j * NB + a) * w + c] -= acc[ci];
+    v[ci] = 0.0;
+    if (c < w) {
+      v[ci] = F[((int64_t)j * NB + a) * w + c] - acc[ci];
+      F[((int64_t)j * NB + a) * w + c] = v[ci];
+    }
   }
   if (j != (UPPER ? k - 1 : k + 1)) return;
-  // block j is now final but for its diagonal step: every thread's update is
-  // visible to the work-group, and T is free, after the barrier
+  // block j is now final but for its diagonal step; once every thread is
+  // done reading T and block k, they take inv(L_jj) and block j
   __syncthreads();
   stage_block(T, LinvP + (size_t)j * NB * NB);
+#pragma unroll
+  for (int ci = 0; ci < FIX_COLS_PER_THREAD; ci++) {
+    const int c = half + 2 * ci;
+    if (c < w) Fs[a][c] = v[ci];
+  }
   __syncthreads();
-  fix_product<UPPER>(T, F, (int64_t)j * NB, w, a, half, true, acc);
-  __syncthreads();  // every read of block j happens before it is overwritten
+  fix_product<UPPER>(T, Fs, w, a, half, true, acc);
 #pragma unroll
   for (int ci = 0; ci < FIX_COLS_PER_THREAD; ci++) {
     const int c = half + 2 * ci;
