@@ -187,25 +187,40 @@ __global__ __launch_bounds__(256) void k_potf2_inv(double* __restrict__ A, int64
 }
 
 // Tile product on MFMA: a 128 x 128 tile computed by 4 waves (64 x 64 each)
-// from column-major operands: acc = sum_l A[i][l] * Bt[j][l] over KD
-// columns (A and Bt are NB-row panels with leading dimension lda / ldb).
+// from column-major operands: acc = sum_l A[i][l] * Bt[j][l] over 4 kd_end
+// columns (A and Bt are NB-row panels with leading dimension lda / ldb;
+// kd_end a multiple of 4).  The operands of k-step kk + 4 are loaded while
+// k-step kk's MFMAs run: a ring of four k-steps, unrolled so that every slot
+// is a fixed set of registers (indexes past the end are clamped to the last
+// k-step; those loads are never used).
 __device__ __forceinline__ void tile_abt(const double* __restrict__ Ap, int64_t lda,
                                          const double* __restrict__ Bp, int64_t ldb,
-                                         int kd_end, d4 (&acc)[4][4], int wr, int wc,
-                                         int lane, double sign) {
+                                         int kd_end, d4 (&acc)[4][4], int wr, int wc, int lane) {
+  constexpr int RING = 4;
   const int r16 = lane % 16, k4 = lane / 16;
-  for (int kk = 0; kk < kd_end; kk++) {
-    double a[4], b[4];
+  auto load = [&](int kk, double (&a)[4], double (&b)[4]) {
+    kk = kk < kd_end ? kk : kd_end - 1;
     const int64_t col = 4 * kk + k4;
 #pragma unroll
     for (int t = 0; t < 4; t++) {
-      a[t] = sign * Ap[(wr * 64 + t * 16 + r16) + col * lda];
+      a[t] = Ap[(wr * 64 + t * 16 + r16) + col * lda];
       b[t] = Bp[(wc * 64 + t * 16 + r16) + col * ldb];
     }
+  };
+  double a[RING][4], b[RING][4];
 #pragma unroll
-    for (int rt = 0; rt < 4; rt++)
+  for (int s = 0; s < RING; s++) load(s, a[s], b[s]);
+  for (int kk0 = 0; kk0 < kd_end; kk0 += RING) {
 #pragma unroll
-      for (int ct = 0; ct < 4; ct++) acc[rt][ct] = MFMA64(a[rt], b[ct], acc[rt][ct]);
+    for (int s = 0; s < RING; s++) {
+#pragma unroll
+      for (int rt = 0; rt < 4; rt++)
+#pragma unroll
+        for (int ct = 0; ct < 4; ct++) acc[rt][ct] = MFMA64(a[s][rt], b[s][ct], acc[rt][ct]);
+      load(kk0 + s + RING, a[s], b[s]);
+      // keep the refill where it is issued, RING k-steps ahead of its use
+      asm volatile("" ::: "memory");
+    }
   }
 }
 
@@ -225,7 +240,7 @@ __global__ __launch_bounds__(256) void k_panel(double* __restrict__ A, int64_t l
 #pragma unroll
     for (int b = 0; b < 4; b++) acc[a][b] = (d4){0, 0, 0, 0};
   // inv(L_kk)[j][l] = 0 for l > j: columns of this wave end at wc*64+63
-  tile_abt(Ap, lda, Li, NB, (wc * 64 + 64) / 4, acc, wr, wc, lane, 1.0);
+  tile_abt(Ap, lda, Li, NB, (wc * 64 + 64) / 4, acc, wr, wc, lane);
   __syncthreads();
 #pragma unroll
   for (int rt = 0; rt < 4; rt++)
@@ -260,6 +275,8 @@ __global__ __launch_bounds__(256) void k_syrk(double* __restrict__ A, int64_t ld
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int wr = wave / 2, wc = wave % 2;
   double* C = A + (int64_t)r * NB + (int64_t)s * NB * lda;
+  // -(-C + A_rk A_sk^T): the same bits as C - A_rk A_sk^T (round to nearest
+  // is symmetric under negation), with unnegated operands in the MFMAs
   d4 acc[4][4];
 #pragma unroll
   for (int rt = 0; rt < 4; rt++)
@@ -267,16 +284,16 @@ __global__ __launch_bounds__(256) void k_syrk(double* __restrict__ A, int64_t ld
     for (int ct = 0; ct < 4; ct++)
 #pragma unroll
       for (int e = 0; e < 4; e++)
-        acc[rt][ct][e] = C[(wr * 64 + rt * 16 + lane / 16 + 4 * e) + (int64_t)(wc * 64 + ct * 16 + lane % 16) * lda];
+        acc[rt][ct][e] = -C[(wr * 64 + rt * 16 + lane / 16 + 4 * e) + (int64_t)(wc * 64 + ct * 16 + lane % 16) * lda];
   tile_abt(A + (int64_t)r * NB + (int64_t)k * NB * lda, lda,
-           A + (int64_t)s * NB + (int64_t)k * NB * lda, lda, NB / 4, acc, wr, wc, lane, -1.0);
+           A + (int64_t)s * NB + (int64_t)k * NB * lda, lda, NB / 4, acc, wr, wc, lane);
 #pragma unroll
   for (int rt = 0; rt < 4; rt++)
 #pragma unroll
     for (int ct = 0; ct < 4; ct++)
 #pragma unroll
       for (int e = 0; e < 4; e++)
-        C[(wr * 64 + rt * 16 + lane / 16 + 4 * e) + (int64_t)(wc * 64 + ct * 16 + lane % 16) * lda] = acc[rt][ct][e];
+        C[(wr * 64 + rt * 16 + lane / 16 + 4 * e) + (int64_t)(wc * 64 + ct * 16 + lane % 16) * lda] = -acc[rt][ct][e];
 }
 
 // Pack L's off-diagonal strips and the inverted diagonal blocks into the
