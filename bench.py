@@ -74,6 +74,8 @@ def parse():
                     help="upper end of the log-uniform m range (the full mix uses 1e7)")
     ap.add_argument("--serve-streams", type=int, default=2,
                     help="serving: compute streams the rounds alternate over")
+    ap.add_argument("--serve-target-cols", type=int, default=32768,
+                    help="genotype columns a serving round aims at (items grow together up to it)")
     ap.add_argument("--serve-inflight", type=int, default=4,
                     help="serving: rounds queued on the device at once")
     ap.add_argument("--serve-ingest", choices=("host", "device"), default="host",
@@ -836,7 +838,7 @@ def serve_bench(args):
         ex = serve.GpuExecutor(precision=prec, phi=phi, ingest=args.serve_ingest,
                                streams=args.serve_streams, slots=args.serve_inflight + 1)
         stats = serve.Scheduler(ex, budget_bytes=(200 << 30) - ex.staging_bytes(),
-                                inflight=args.serve_inflight,
+                                inflight=args.serve_inflight, target_cols=args.serve_target_cols,
                                 log=lambda msg, prec=prec: log(f"[{prec}] {msg}")).run(jobs)
         stats["timeline"] = ex.timeline_summary()
         log(f"[{prec}] timeline: {stats['timeline']}")
@@ -857,7 +859,7 @@ def serve_bench(args):
                    "p": [4, 20], "m": [1e5, args.serve_m_max], "h": [0.2, 0.8],
                    "hbm_budget_bytes": 200 << 30, "ingest": args.serve_ingest,
                    "compute_streams": args.serve_streams, "rounds_inflight": args.serve_inflight,
-                   "parallelism": "1 GPU"},
+                   "round_target_cols": args.serve_target_cols, "parallelism": "1 GPU"},
         "forms": res,
     }
     print(json.dumps(out), flush=True)

@@ -125,7 +125,7 @@ class Scheduler:
 
     def __init__(self, executor: Executor, budget_bytes: int, max_items: int = 16,
                  inflight: int = 4, clock=time.monotonic, sleep=time.sleep,
-                 target_cols: int = 16384, max_mult: int = 16, log=None):
+                 target_cols: int = 32768, max_mult: int = 16, log=None):
         self.ex = executor
         self.budget = int(budget_bytes)
         self.max_items = max_items
@@ -133,8 +133,10 @@ class Scheduler:
         self.clock = clock
         self.sleep = sleep
         # a round should give the device at least target_cols genotype
-        # columns; with few active jobs every job's item grows by a common
-        # factor (up to max_mult), which keeps the items of a round equal
+        # columns (32,768: one 128-column slab per compute unit, the widest
+        # and, per column, fastest form of the solve); with few active jobs
+        # every job's item grows by a common factor (up to max_mult), which
+        # keeps the items of a round equal
         self.target_cols = target_cols
         self.max_mult = max_mult
         self.log = log
