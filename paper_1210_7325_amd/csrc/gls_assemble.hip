@@ -26,7 +26,10 @@ namespace gls {
 constexpr int AS_WAVES = 8;
 constexpr int AS_COLS = AS_GROUP_COLS;     // columns per work-group (4 tiles of 16)
 // row octets in flight per wave (fewer with two F tiles: registers)
-template <int ET> constexpr int as_depth() { return ET == 1 ? 4 : 3; }
+template <int ET> constexpr int as_depth() { return 2; }
+// columns reduced per pass (two passes: the reduction buffer is half the
+// group, so that two work-groups fit one compute unit)
+constexpr int AS_RED_COLS = AS_COLS / 2;
 constexpr int AS_DOTS = 2 * 16 + 16;       // per column: up to 32 F dots + 16 Gram entries
 
 // Cholesky of a p x p SPD matrix held by one wavefront, lane j holding
@@ -134,9 +137,12 @@ __device__ __forceinline__ void mfma_dots(LoadA loadA, const double* __restrict_
       g1[et] = e < ldf ? p1[e] : 0.0;
     }
   };
+  // every fetch is issued on every path (octets past the end clamped to the
+  // last one and never used), so that the waits the compiler places for a
+  // stage's operands do not also cover the fetches of the stages after it
+  auto clamp = [&](int64_t o) { return o < noct ? o : noct - 1; };
 #pragma unroll
-  for (int st = 0; st < DEPTH; st++)
-    if (wave + 8 * st < noct) fetch(wave + 8 * st, av[st], f0[st], f1[st]);
+  for (int st = 0; st < DEPTH; st++) fetch(clamp(wave + 8 * st), av[st], f0[st], f1[st]);
   for (int64_t o0 = wave; o0 < noct; o0 += 8 * DEPTH) {
 #pragma unroll
     for (int st = 0; st < DEPTH; st++) {
@@ -154,9 +160,8 @@ __device__ __forceinline__ void mfma_dots(LoadA loadA, const double* __restrict_
             acc[ct][ET] = MFMA64(av[st][ct].y, av[st][ct].y, acc[ct][ET]);
           }
         }
-        const int64_t on = o + 8 * DEPTH;
-        if (on < noct) fetch(on, av[st], f0[st], f1[st]);
       }
+      fetch(clamp(o + 8 * DEPTH), av[st], f0[st], f1[st]);
     }
   }
 }
@@ -167,34 +172,38 @@ __device__ __forceinline__ void mfma_dots(LoadA loadA, const double* __restrict_
 // for q < gram_pR, c0 the first column of c's problem in its tile.
 template <int ET>
 __device__ __forceinline__ void reduce_slice(const d4 (&acc)[4][ET + 1], int et, int wave, int lane,
-                                             double (*red)[AS_COLS][17],
+                                             double (*red)[AS_RED_COLS][17],
                                              double (*dots)[AS_DOTS], int elim, int base,
                                              int gram_pR) {
   const int r = lane / 16, cl = lane % 16;
 #pragma unroll
-  for (int ct = 0; ct < 4; ct++)
+  for (int h = 0; h < AS_COLS / AS_RED_COLS; h++) {
+    constexpr int TPH = AS_RED_COLS / 16;  // column tiles per pass
 #pragma unroll
-    for (int i = 0; i < 4; i++)
+    for (int ct = h * TPH; ct < (h + 1) * TPH; ct++)
 #pragma unroll
-      for (int k = 0; k <= ET; k++)
-        if (k == et) red[wave][16 * ct + r + 4 * i][cl] = acc[ct][k][i];
-  __syncthreads();
-  for (int idx = threadIdx.x; idx < AS_COLS * 16; idx += 64 * AS_WAVES) {
-    const int c = idx / 16, e = idx % 16;
-    if (gram_pR == 0) {
-      if (16 * et + e < elim) {
+      for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int k = 0; k <= ET; k++)
+          if (k == et) red[wave][16 * (ct - h * TPH) + r + 4 * i][cl] = acc[ct][k][i];
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < AS_RED_COLS * 16; idx += 64 * AS_WAVES) {
+      const int cr = idx / 16, e = idx % 16, c = h * AS_RED_COLS + cr;
+      if (gram_pR == 0) {
+        if (16 * et + e < elim) {
+          double v = 0.0;
+          for (int w = 0; w < AS_WAVES; w++) v += red[w][cr][e];
+          dots[c][16 * et + e] = v;
+        }
+      } else if (e < gram_pR && c % 16 < 16 / gram_pR * gram_pR) {   // columns of a problem
+        const int c0 = (c % 16) - (c % 16) % gram_pR;   // problem's first column in the tile
         double v = 0.0;
-        for (int w = 0; w < AS_WAVES; w++) v += red[w][c][e];
-        dots[c][16 * et + e] = v;
+        for (int w = 0; w < AS_WAVES; w++) v += red[w][cr][c0 + e];
+        dots[c][base + e] = v;
       }
-    } else if (e < gram_pR && c % 16 < 16 / gram_pR * gram_pR) {   // columns of a problem
-      const int c0 = (c % 16) - (c % 16) % gram_pR;   // problem's first column in the tile
-      double v = 0.0;
-      for (int w = 0; w < AS_WAVES; w++) v += red[w][c][c0 + e];
-      dots[c][base + e] = v;
     }
+    __syncthreads();
   }
-  __syncthreads();
 }
 
 // REFINE = false: the FP64 path.  REFINE = true: the FP32_REFINE form; the
@@ -205,8 +214,8 @@ __device__ __forceinline__ void reduce_slice(const d4 (&acc)[4][ET + 1], int et,
 //   r = c' - S' b0,  d = (G G^T)^{-1} r,  b' = b0 + d,
 // then b_L[icol] -= s^T b'_R undoes the centering.
 template <bool REFINE, int ET>
-__global__ __launch_bounds__(64 * AS_WAVES) void k_assemble_solve(const AsmTable tab) {
-  __shared__ double red[AS_WAVES][AS_COLS][17];
+__global__ __launch_bounds__(64 * AS_WAVES, ET == 1 ? 4 : 2) void k_assemble_solve(const AsmTable tab) {
+  __shared__ double red[AS_WAVES][AS_RED_COLS][17];
   __shared__ double dots[AS_COLS][AS_DOTS];
 
   int jb = 0;
