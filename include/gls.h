@@ -239,9 +239,10 @@ int gls_kernel_time(gls_handle h, int kind, double* ms, int64_t* launches);
  * problems whose genotypes live on the host (or on disk) and are produced
  * on demand by `fill`, with double buffering: while block j is solved on
  * h's stream, block j+1 is filled into pinned host memory and copied to the
- * device on a second stream, and the b of block j-1 is copied back on a
- * third stream and handed to `sink` (Alg. 8: async read of the next block,
- * wait for the current one, compute, async write, wait for the previous).
+ * device on a second stream, and the b of block j-1, which the device wrote
+ * straight into pinned host memory, is handed to `sink` (Alg. 8: async read
+ * of the next block, wait for the current one, compute, async write, wait
+ * for the previous).
  * fill(fill_ctx, snp0, nsnp, buf, ld) writes the n x (nsnp*p_R) int8
  *   genotypes of problems snp0.. into pinned host memory buf (column j at
  *   buf + j*ld, ld = n); it returns 0, or nonzero to abort the stream.
@@ -256,8 +257,8 @@ int gls_kernel_time(gls_handle h, int kind, double* ms, int64_t* launches);
  * snp_begin may be any block boundary of an earlier run: a stream that was
  * aborted resumes after the last block its sink accepted and yields the
  * same bits.  SYNCHRONOUS.  The library allocates (and frees) two pinned
- * input and output buffers, two device input and output buffers and two
- * streams.  stats (nullable) receives wall, fill, sink and wait times. */
+ * input and output buffers, two device input buffers and one stream.
+ * stats (nullable) receives wall, fill, sink and wait times. */
 typedef int (*gls_fill_fn)(void* fill_ctx, int64_t snp0, int64_t nsnp, int8_t* buf, int64_t ld);
 typedef int (*gls_sink_fn)(void* sink_ctx, int64_t snp0, int64_t nsnp, const double* b,
                            const int32_t* info);
@@ -268,7 +269,8 @@ typedef struct {
   double wait_ms;       /* host time blocked on device work (exposed compute) */
   int64_t blocks;
   int64_t bytes_h2d;
-  int64_t bytes_d2h;
+  int64_t bytes_d2h;    /* results handed to the host (the assembly writes them
+                           straight into pinned host memory)                */
 } gls_stream_stats;
 
 int gls_solve_stream(gls_handle h, int64_t snp_begin, int64_t snp_end, int64_t block,

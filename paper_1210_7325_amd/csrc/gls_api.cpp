@@ -819,33 +819,31 @@ int gls_solve_stream(gls_handle h, int64_t snp_begin, int64_t snp_end, int64_t b
   int rc = ensure_workspace(h, cols);
   if (rc) return rc;
 
+  // Results go from the assembly kernel straight into pinned host memory
+  // (mapped into the device's address space): a device-to-host copy would
+  // be a copy kernel, and with the solve kernel holding every compute unit
+  // it could not start before the next superblock's solve had finished,
+  // which kept the host from handing over results and filling the next
+  // input while the device worked.
   int8_t* hin[2] = {nullptr, nullptr};
   int8_t* din[2] = {nullptr, nullptr};
   double* hB[2] = {nullptr, nullptr};
-  double* dB[2] = {nullptr, nullptr};
   int32_t* hinfo[2] = {nullptr, nullptr};
-  int32_t* dinfo[2] = {nullptr, nullptr};
-  hipStream_t s_in = nullptr, s_out = nullptr;
-  hipEvent_t ev_in[2] = {nullptr, nullptr}, ev_comp[2] = {nullptr, nullptr},
-             ev_out[2] = {nullptr, nullptr};
+  hipStream_t s_in = nullptr;
+  hipEvent_t ev_in[2] = {nullptr, nullptr}, ev_comp[2] = {nullptr, nullptr};
   const size_t in_bytes = (size_t)n * cols, out_n = (size_t)sbk * t * p;
   auto cleanup = [&]() {
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     if (s_in) (void)hipStreamSynchronize(s_in);
-    if (s_out) (void)hipStreamSynchronize(s_out);
     for (int i = 0; i < 2; i++) {
       if (hin[i]) (void)hipHostFree(hin[i]);
       if (hB[i]) (void)hipHostFree(hB[i]);
       if (hinfo[i]) (void)hipHostFree(hinfo[i]);
       dfree(din[i]);
-      dfree(dB[i]);
-      dfree(dinfo[i]);
       if (ev_in[i]) (void)hipEventDestroy(ev_in[i]);
       if (ev_comp[i]) (void)hipEventDestroy(ev_comp[i]);
-      if (ev_out[i]) (void)hipEventDestroy(ev_out[i]);
     }
     if (s_in) (void)hipStreamDestroy(s_in);
-    if (s_out) (void)hipStreamDestroy(s_out);
   };
 #define STREAM_CHK(x)               \
   do {                              \
@@ -860,14 +858,10 @@ int gls_solve_stream(gls_handle h, int64_t snp_begin, int64_t snp_end, int64_t b
     STREAM_CHK(hipHostMalloc(reinterpret_cast<void**>(&hB[i]), out_n * sizeof(double), hipHostMallocDefault));
     STREAM_CHK(hipHostMalloc(reinterpret_cast<void**>(&hinfo[i]), sbk * sizeof(int32_t), hipHostMallocDefault));
     STREAM_CHK(hipMalloc(reinterpret_cast<void**>(&din[i]), in_bytes));
-    STREAM_CHK(hipMalloc(reinterpret_cast<void**>(&dB[i]), out_n * sizeof(double)));
-    STREAM_CHK(hipMalloc(reinterpret_cast<void**>(&dinfo[i]), sbk * sizeof(int32_t)));
     STREAM_CHK(hipEventCreateWithFlags(&ev_in[i], hipEventDisableTiming));
     STREAM_CHK(hipEventCreateWithFlags(&ev_comp[i], hipEventDisableTiming));
-    STREAM_CHK(hipEventCreateWithFlags(&ev_out[i], hipEventDisableTiming));
   }
   STREAM_CHK(hipStreamCreateWithFlags(&s_in, hipStreamNonBlocking));
-  STREAM_CHK(hipStreamCreateWithFlags(&s_out, hipStreamNonBlocking));
 
   const int64_t nsb = (snp_end - snp_begin + sbk - 1) / sbk;
   auto sb_snp0 = [&](int64_t j) { return snp_begin + j * sbk; };
@@ -875,7 +869,7 @@ int gls_solve_stream(gls_handle h, int64_t snp_begin, int64_t snp_end, int64_t b
   auto drain = [&](int64_t j) -> int {
     const int sj = (int)(j % 2);
     const auto tw = clk::now();
-    hipError_t e = hipEventSynchronize(ev_out[sj]);
+    hipError_t e = hipEventSynchronize(ev_comp[sj]);
     st.wait_ms += ms_since(tw);
     if (e != hipSuccess) return hip_code(e);
     const int64_t len = sb_len(j);
@@ -914,21 +908,16 @@ int gls_solve_stream(gls_handle h, int64_t snp_begin, int64_t snp_end, int64_t b
     STREAM_CHK(hipMemcpyAsync(din[sj], hin[sj], (size_t)n * len * p_R, hipMemcpyHostToDevice, s_in));
     STREAM_CHK(hipEventRecord(ev_in[sj], s_in));
     st.bytes_h2d += n * len * p_R;
-    // solve on the handle's stream after the copy; device output sj is
-    // free once the copy-back of superblock j-2 has finished
+    // solve on the handle's stream after the copy; the pinned output sj was
+    // handed over (drained) after superblock j-2, before this one was issued
     STREAM_CHK(hipStreamWaitEvent(h->stream, ev_in[sj], 0));
-    if (j >= 2) STREAM_CHK(hipStreamWaitEvent(h->stream, ev_out[sj], 0));
-    gls_work w{h, len, p_R, din[sj], n, dB[sj], p, dinfo[sj]};
+    gls_work w{h, len, p_R, din[sj], n, hB[sj], p, hinfo[sj]};
     rc = launch_rounds(&w, 1, h->stream, h);
     if (rc) {
       cleanup();
       return rc;
     }
     STREAM_CHK(hipEventRecord(ev_comp[sj], h->stream));
-    STREAM_CHK(hipStreamWaitEvent(s_out, ev_comp[sj], 0));
-    STREAM_CHK(hipMemcpyAsync(hB[sj], dB[sj], (size_t)len * t * p * sizeof(double), hipMemcpyDeviceToHost, s_out));
-    STREAM_CHK(hipMemcpyAsync(hinfo[sj], dinfo[sj], (size_t)len * sizeof(int32_t), hipMemcpyDeviceToHost, s_out));
-    STREAM_CHK(hipEventRecord(ev_out[sj], s_out));
     // hand over the previous superblock while this one computes
     if (j >= 1 && (rc = drain(j - 1))) {
       cleanup();
