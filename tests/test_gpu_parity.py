@@ -264,15 +264,21 @@ def test_genotypes_with_a_padded_leading_dimension(G, prec, n, pad, offset):
     c.free()
 
 
-def test_multi_cohort_launch_equals_single(G):
-    say("multi")
+@pytest.mark.parametrize("prec,slab", [("fp64", 0), ("fp64", 128), ("fp32_refine", 128)])
+def test_multi_cohort_launch_equals_single(G, prec, slab):
+    """One launch over cohorts of different n (K = 3, 6 and 2 row blocks:
+    with 128-column slabs the paired-block solve meets a lone last block,
+    three pairs, and a last block left to the last-block kernel in the same
+    launch) gives each cohort the bits of its own launch."""
+    say("multi", prec, slab)
     from paper_1210_7325_amd import gls
     probs = [small_problem(n, pL=pL, pR=pR, m=m, t=t, seed=i)
              for i, (n, pL, pR, t, m) in enumerate([(300, 3, 1, 1, 100), (700, 5, 2, 2, 64),
                                                       (129, 2, 1, 1, 30)])]
     alone, items, cohorts = [], [], []
     for (w, M, XL, Y, XR), pR in zip(probs, (1, 2, 1)):
-        c = gls.Cohort(to_dev(M)).whiten_fixed(to_dev(XL), to_dev(Y))
+        c = gls.Cohort(to_dev(M), precision=prec).whiten_fixed(to_dev(XL), to_dev(Y), intercept_col=0)
+        c.set_slab_cols(slab)
         dXR = to_dev(XR)
         B, _ = c.solve_block(dXR, p_R=pR)
         alone.append(B.cpu().numpy())
