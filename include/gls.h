@@ -234,6 +234,19 @@ int gls_set_slab_cols(gls_handle h, int cols);
 int gls_set_kernel_timing(gls_handle h, int enable);
 int gls_kernel_time(gls_handle h, int kind, double* ms, int64_t* launches);
 
+/* The same record one launch at a time, in launch order.  For each of the
+ * first `cap` recorded launches of `kind`: ms[i] its bracketed duration in
+ * milliseconds, cols[i] the genotype columns (right-hand sides, nsnp * p_R
+ * summed over the launch's work items) it processed, slab[i] its columns
+ * per work-group of the triangular solve.  *count receives the number of
+ * recorded launches of that kind, which may exceed cap (cap = 0 only counts).
+ * The caller owns the three arrays (host memory, cap entries each).
+ * Synchronizes on the recorded events of the returned launches.
+ * Errors: -1 h NULL, -2 kind not 0 or 1, -3 cap < 0, -4 an array NULL with
+ * cap > 0, -7 count NULL, GLS_E_HIP. */
+int gls_kernel_launches(gls_handle h, int kind, int64_t cap, double* ms, int64_t* cols, int* slab,
+                        int64_t* count);
+
 /* ---- streamed genotypes (out-of-core, Sec. 4, Alg. 8) -------------------
  * Solves problems [snp_begin, snp_end) of h's cohort in blocks of `block`
  * problems whose genotypes live on the host (or on disk) and are produced

@@ -45,6 +45,8 @@ struct Cohort {
 struct TimedLaunch {
   hipEvent_t a = nullptr, b = nullptr;
   int kind = 0;
+  int slab = 0;                // columns per work-group of the launch
+  int64_t cols = 0;            // genotype columns (right-hand sides) the launch processed
 };
 
 struct gls_handle_s {
@@ -228,7 +230,7 @@ int check_block(gls_handle h, int64_t nsnp, int64_t pR, const int8_t* X_R, int64
 struct TimedScope {
   gls_handle h;
   TimedLaunch* p = nullptr;
-  TimedScope(gls_handle h_, int kind) : h(h_) {
+  TimedScope(gls_handle h_, int kind, int64_t cols, int slab) : h(h_) {
     if (!h || !h->timing) return;
     if (h->ntimed == h->timed.size()) {
       TimedLaunch t;
@@ -237,6 +239,8 @@ struct TimedScope {
     }
     p = &h->timed[h->ntimed++];
     p->kind = kind;
+    p->cols = cols;
+    p->slab = slab;
     (void)hipEventRecord(p->a, h->stream);
   }
   void end() {
@@ -300,11 +304,12 @@ int launch_items(const gls_work* items, int64_t count, hipStream_t st, gls_handl
   AsmTable at;
   XzTable xt;
   tab.njobs = at.njobs = xt.njobs = 0;
-  int64_t slabs = 0, groups = 0, xgroups = 0;
+  int64_t slabs = 0, groups = 0, xgroups = 0, cols = 0;
   for (int64_t i = 0; i < count; i++) {
     const gls_work& w = items[i];
     if (w.nsnp == 0) continue;
     const int64_t ncols = w.nsnp * w.p_R;
+    cols += ncols;
     const Workspace wsi = ws ? *ws : own_workspace(w.h);
     if (refine) {
       xt.j[xt.njobs++] = make_xz(w.h, wsi, xgroups, ncols, w.X_R, w.ldxr);
@@ -321,15 +326,15 @@ int launch_items(const gls_work* items, int64_t count, hipStream_t st, gls_handl
   if (th) th->stream = st;  // timing events go to the launch stream
   hipError_t e = hipSuccess;
   if (refine) {
-    TimedScope tx(th, 1);
+    TimedScope tx(th, 1, cols, C);
     e = launch_xz_shift(xt, xgroups, st);
   }
   if (e == hipSuccess) {
-    TimedScope t0(th, 0);
+    TimedScope t0(th, 0, cols, C);
     e = refine ? launch_trsm_mixed(tab, slabs, C, st) : launch_trsm_i8(tab, slabs, C, st);
   }
   if (e == hipSuccess) {
-    TimedScope t1(th, 1);
+    TimedScope t1(th, 1, cols, C);
     e = launch_assemble_solve(at, groups, refine, st);
   }
   if (th) th->stream = keep;
@@ -711,7 +716,7 @@ int gls_whiten_block(gls_handle h, int64_t ncols, const int8_t* X, int64_t ldx, 
   tab.j[0] = make_job(h, own_workspace(h), 0, ncols, X, ldx);
   const gls_work item{h, ncols, 1, X, ldx, nullptr, 0, nullptr};
   const int C = slab_cols_for(&item, 1);
-  TimedScope t0(h, 0);
+  TimedScope t0(h, 0, ncols, C);
   if (h->c->prec == GLS_FP32_REFINE) {
     // plain L^{-1} X: no centering shift
     HIPCHK(hipMemsetAsync(h->shift, 0, sizeof(double) * ncols, h->stream));
@@ -743,7 +748,7 @@ int gls_whiten_block_f64(gls_handle h, int64_t ncols, const double* X, int64_t l
   const gls_work item{h, ncols, 1, nullptr, ldx, nullptr, 0, nullptr};
   int C = slab_cols_for(&item, 1);
   if (C == 32) C = 64;  // FP64 right-hand sides come in 16-, 64- and 128-column slabs
-  TimedScope t0(h, 0);
+  TimedScope t0(h, 0, ncols, C);
   HIPCHK(launch_trsm_f64(tab, (ncols + C - 1) / C, C, h->stream));
   t0.end();
   HIPCHK(launch_slab_to_colmajor(h->W, C, h->c->n_pad, h->c->n, 0, ncols, W, ldw, h->stream));
@@ -784,6 +789,31 @@ int gls_kernel_time(gls_handle h, int kind, double* ms, int64_t* launches) {
   }
   *ms = sum;
   *launches = cnt;
+  return GLS_OK;
+}
+
+int gls_kernel_launches(gls_handle h, int kind, int64_t cap, double* ms, int64_t* cols, int* slab,
+                        int64_t* count) {
+  if (!h) return -1;
+  if (kind != 0 && kind != 1) return -2;
+  if (cap < 0) return -3;
+  if (cap > 0 && (!ms || !cols || !slab)) return -4;
+  if (!count) return -7;
+  int64_t cnt = 0;
+  for (size_t i = 0; i < h->ntimed; i++) {
+    const TimedLaunch& p = h->timed[i];
+    if (p.kind != kind) continue;
+    if (cnt < cap) {
+      HIPCHK(hipEventSynchronize(p.b));
+      float f = 0.f;
+      HIPCHK(hipEventElapsedTime(&f, p.a, p.b));
+      ms[cnt] = f;
+      cols[cnt] = p.cols;
+      slab[cnt] = p.slab;
+    }
+    cnt++;
+  }
+  *count = cnt;
   return GLS_OK;
 }
 

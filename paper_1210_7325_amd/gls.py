@@ -38,6 +38,7 @@ EXPORTS = ("gls_factor", "gls_whiten_fixed", "gls_solve_block", "gls_solve_block
            "gls_strerror", "gls_copy_factor", "gls_copy_fixed", "gls_whiten_block",
            "gls_whiten_block_f64",
            "gls_solve_multi", "gls_set_slab_cols", "gls_set_kernel_timing", "gls_kernel_time",
+           "gls_kernel_launches",
            "gls_solve_stream", "gls_file_open", "gls_file_fill", "gls_file_stats",
            "gls_file_close", "gls_writer_open", "gls_writer_sink", "gls_writer_close")
 
@@ -96,6 +97,9 @@ def lib() -> ctypes.CDLL:
             "gls_set_kernel_timing": (_int, [_p, _int]),
             "gls_kernel_time": (_int, [_p, _int, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(_i64)]),
+            "gls_kernel_launches": (_int, [_p, _int, _i64, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(_i64), ctypes.POINTER(_int),
+                                           ctypes.POINTER(_i64)]),
             "gls_solve_stream": (_int, [_p, _i64, _i64, _i64, _i64, _p, _p, _p, _p,
                                         ctypes.POINTER(gls_stream_stats)]),
             "gls_file_open": (_int, [ctypes.POINTER(_p), ctypes.c_char_p, _i64, _i64, _i64, _int,
@@ -214,6 +218,18 @@ def gls_kernel_time(h, kind) -> Tuple[int, float, int]:
     ms, cnt = ctypes.c_double(), _i64()
     rc = lib().gls_kernel_time(h, kind, ctypes.byref(ms), ctypes.byref(cnt))
     return rc, ms.value, cnt.value
+
+
+def gls_kernel_launches(h, kind) -> Tuple[int, list]:
+    """[(ms, cols, slab)] of every recorded launch of `kind`, in launch order."""
+    cnt = _i64()
+    rc = lib().gls_kernel_launches(h, kind, 0, None, None, None, ctypes.byref(cnt))
+    if rc or cnt.value == 0:
+        return rc, []
+    n = cnt.value
+    ms, cols, slab = (ctypes.c_double * n)(), (_i64 * n)(), (_int * n)()
+    rc = lib().gls_kernel_launches(h, kind, n, ms, cols, slab, ctypes.byref(cnt))
+    return rc, [(ms[i], cols[i], slab[i]) for i in range(min(n, cnt.value))]
 
 
 def gls_solve_stream(h, snp_begin, snp_end, block, p_R, fill, fill_ctx, sink, sink_ctx):
@@ -407,6 +423,12 @@ class Cohort:
         rc, ms, cnt = gls_kernel_time(self.h, kind)
         _chk(rc, "gls_kernel_time")
         return ms, cnt
+
+    def kernel_launches(self, kind: int) -> list:
+        """Per-launch record of the kernel timing: [(ms, cols, slab)]."""
+        rc, out = gls_kernel_launches(self.h, kind)
+        _chk(rc, "gls_kernel_launches")
+        return out
 
     def fork(self, stream=None) -> "Cohort":
         torch = _torch()

@@ -60,6 +60,7 @@ def test_argument_validation_without_device():
     assert L.gls_set_slab_cols(None, 64) == -1
     assert L.gls_set_kernel_timing(None, 1) == -1
     assert L.gls_kernel_time(None, 0, None, None) == -1
+    assert L.gls_kernel_launches(None, 0, 0, None, None, None, None) == -1
     L.gls_free(None)
 
 

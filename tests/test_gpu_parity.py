@@ -435,3 +435,38 @@ def test_rounds_split_items_bitwise(G, prec, pR, t):
     err = orc.relative_error(outs[0][0][idx], ref)
     say("max rel err", err.max())
     assert err.max() < (1e-10 if prec == "fp64" else 1e-8)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_refine"])
+def test_kernel_launch_record(G, prec):
+    """The per-launch timing record (gls_kernel_launches): one entry per
+    launch of the triangular solve, in launch order, whose columns add up to
+    the call's right-hand sides, whose durations add up to gls_kernel_time's
+    sum, and whose slab widths show the rounds: a first launch of at most
+    one slab per compute unit, then the rest at a width of its own."""
+    from paper_1210_7325_amd import gls
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    m = cus * 64 * 11 // 10
+    say("launch record", prec, "cus", cus, "problems", m)
+    w, M, XL, Y, XR = small_problem(300, m=m, seed=23)
+    c = gls.Cohort(to_dev(M), precision=prec).whiten_fixed(to_dev(XL), to_dev(Y), intercept_col=0)
+    c.set_kernel_timing(True)
+    B, info = c.solve_block(to_dev(XR), p_R=1)
+    torch.cuda.synchronize()
+    rec = c.kernel_launches(0)
+    ms, cnt = c.kernel_time(0)
+    asm = c.kernel_launches(1)
+    c.free()
+    say("record", rec)
+    assert np.all(info.cpu().numpy() == 0)
+    assert len(rec) == cnt >= 2
+    assert sum(r[1] for r in rec) == m
+    assert abs(sum(r[0] for r in rec) - ms) <= 1e-6 * ms
+    assert all(r[0] > 0 and r[2] in (16, 32, 64, 128) for r in rec)
+    assert rec[0][1] <= cus * rec[0][2]
+    # kind 1: each launch of the solve is followed by one of the assembly,
+    # preceded in the FP32_REFINE form by the centering pre-pass
+    per = 2 if prec == "fp32_refine" else 1
+    assert len(asm) == per * len(rec)
+    assert [r[1] for r in asm[per - 1::per]] == [r[1] for r in rec]
+    assert [r[1] for r in asm[::per]] == [r[1] for r in rec]
