@@ -331,7 +331,13 @@ constexpr int PAIR_SLOTS = 3;             // stage slots of 48 KB
 // over the same npairs k-step pairs of W, operands staged through LDS as in
 // gemm_staged_f64: a stage is two pairs, i.e. 2 (2 NB/16 + C/16) chunks of
 // 1 KB, copied S - 1 stages ahead; the barrier sits in the middle of the
-// stage.
+// stage.  Each half-stage's 32 MFMAs go out in eight groups of four (one
+// output tile each), and the other instructions of the half sit between
+// the groups: the LDS reads of the next half's operands (two after each of
+// the first four groups) and, after the barrier, this wave's copies of
+// stage st + S (one after each of groups 2-7).  Issued as a block before
+// the MFMAs, they left the matrix pipe idle while both waves of a SIMD
+// issued them (about 8% of the loop's cycles).
 template <int C, int WR, int WC, int S>
 __device__ __forceinline__ void gemm_staged_pair(const double* __restrict__ Lk0, const double* __restrict__ Lk1,
                                                  const double* __restrict__ Wslab, int npairs,
@@ -343,69 +349,81 @@ __device__ __forceinline__ void gemm_staged_pair(const double* __restrict__ Lk0,
   constexpr int NW = WR * WC;
   constexpr int CL = G * NT;             // chunks of one strip per stage
   constexpr int CPS = 2 * CL + G * CTS;  // chunks per stage
-  static_assert(CPS % NW == 0, "every wave copies the same number of chunks");
+  static_assert(CPS % NW == 0 && CL % NW == 0, "every wave copies the same chunks of each operand");
   constexpr int LPW = CPS / NW;
+  constexpr int NG = RT * CT;            // MFMA groups per half-stage
+  constexpr int NR = 2 * RT + CT;        // LDS reads per half-stage
+  static_assert(NG == 8 && NR == 8 && LPW == 6, "the interleave places 2 reads after groups 0-3 and "
+                                                "1 copy after groups 2-7");
   double(*ring)[CPS * 128] = reinterpret_cast<double(*)[CPS * 128]>(ring_base);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x % 64;
   __builtin_assume(wave >= 0 && wave < NW);
   const int wr = wave / WC, wc = wave % WC;
   const int nst = npairs / G;
-  // this wave's copies of stage st (clamped to the last: the tail copies are
-  // never read) into slot st % S: chunks [0, CL) strip k, [CL, 2 CL) strip
-  // k+1, then the W tiles
-  auto issue = [&](int st) {
+  // copy i of this wave (chunk c = wave + i NW) of stage st (clamped to the
+  // last: the tail copies are never read) into slot st % S: chunks [0, CL)
+  // strip k, [CL, 2 CL) strip k+1, then the W tiles
+  auto issue_one = [&](int st, int i) {
     const int sl = st % S;
     st = st < nst ? st : nst - 1;
-#pragma unroll
-    for (int i = 0; i < LPW; i++) {
-      const int c = wave + i * NW;
-      const double* src = c < CL       ? Lk0 + ((size_t)st * CL + c) * 128 + lane * 2
-                          : c < 2 * CL ? Lk1 + ((size_t)st * CL + (c - CL)) * 128 + lane * 2
-                                       : Wslab + ((size_t)st * G * CTS + (c - 2 * CL)) * 128 + lane * 2;
-      chunk_to_lds(src, &ring[sl][c * 128]);
-    }
+    const int c = wave + i * NW;
+    const double* src = i < CL / NW       ? Lk0 + ((size_t)st * CL + c) * 128 + lane * 2
+                        : i < 2 * CL / NW ? Lk1 + ((size_t)st * CL + (c - CL)) * 128 + lane * 2
+                                          : Wslab + ((size_t)st * G * CTS + (c - 2 * CL)) * 128 + lane * 2;
+    chunk_to_lds(src, &ring[sl][c * 128]);
   };
-  auto read_pair = [&](int st, int g, d2 (&a0)[RT], d2 (&a1)[RT], d2 (&b)[CT]) {
+  // operand fragment r of half g of stage st: r < RT rows of strip k,
+  // r < 2 RT rows of strip k+1, then the W column tiles
+  auto read_one = [&](int st, int g, int r, d2 (&a0)[RT], d2 (&a1)[RT], d2 (&b)[CT]) {
     const double* __restrict__ slot = ring[st % S];
-#pragma unroll
-    for (int rt = 0; rt < RT; rt++) {
-      a0[rt] = *reinterpret_cast<const d2*>(slot + (g * NT + wr * RT + rt) * 128 + lane * 2);
-      a1[rt] = *reinterpret_cast<const d2*>(slot + (CL + g * NT + wr * RT + rt) * 128 + lane * 2);
-    }
-#pragma unroll
-    for (int ct = 0; ct < CT; ct++)
-      b[ct] = *reinterpret_cast<const d2*>(slot + (2 * CL + g * CTS + wc * CT + ct) * 128 + lane * 2);
+    if (r < RT)
+      a0[r] = *reinterpret_cast<const d2*>(slot + (g * NT + wr * RT + r) * 128 + lane * 2);
+    else if (r < 2 * RT)
+      a1[r - RT] = *reinterpret_cast<const d2*>(slot + (CL + g * NT + wr * RT + r - RT) * 128 + lane * 2);
+    else
+      b[r - 2 * RT] = *reinterpret_cast<const d2*>(slot + (2 * CL + g * CTS + wc * CT + r - 2 * RT) * 128 + lane * 2);
   };
-  auto mfma_pair = [&](const d2 (&a0)[RT], const d2 (&a1)[RT], const d2 (&b)[CT]) {
-#pragma unroll
-    for (int rt = 0; rt < RT; rt++)
-#pragma unroll
-      for (int ct = 0; ct < CT; ct++) {
-        acc0[rt][ct] = MFMA64(a0[rt].x, b[ct].x, acc0[rt][ct]);
-        acc1[rt][ct] = MFMA64(a1[rt].x, b[ct].x, acc1[rt][ct]);
-        acc0[rt][ct] = MFMA64(a0[rt].y, b[ct].y, acc0[rt][ct]);
-        acc1[rt][ct] = MFMA64(a1[rt].y, b[ct].y, acc1[rt][ct]);
-      }
+  // group g8: the four MFMAs of output tile (g8 / CT, g8 % CT) of both blocks
+  auto mfma_group = [&](int g8, const d2 (&a0)[RT], const d2 (&a1)[RT], const d2 (&b)[CT]) {
+    const int rt = g8 / CT, ct = g8 % CT;
+    acc0[rt][ct] = MFMA64(a0[rt].x, b[ct].x, acc0[rt][ct]);
+    acc1[rt][ct] = MFMA64(a1[rt].x, b[ct].x, acc1[rt][ct]);
+    acc0[rt][ct] = MFMA64(a0[rt].y, b[ct].y, acc0[rt][ct]);
+    acc1[rt][ct] = MFMA64(a1[rt].y, b[ct].y, acc1[rt][ct]);
   };
 #pragma unroll
-  for (int st = 0; st < S; st++) issue(st);
+  for (int st = 0; st < S; st++)
+#pragma unroll
+    for (int i = 0; i < LPW; i++) issue_one(st, i);
   wait_vm_lgkm0<(S - 1) * LPW>();
   barrier_only();
   d2 p0[RT], q0[RT], b0[CT], p1[RT], q1[RT], b1[CT];
-  read_pair(0, 0, p0, q0, b0);
+#pragma unroll
+  for (int r = 0; r < NR; r++) read_one(0, 0, r, p0, q0, b0);
   for (int st = 0; st < nst; st++) {
     wait_lgkm0();
-    read_pair(st, 1, p1, q1, b1);
-    __builtin_amdgcn_sched_barrier(0);
-    mfma_pair(p0, q0, b0);
-    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int g8 = 0; g8 < NG; g8++) {
+      mfma_group(g8, p0, q0, b0);
+      if (g8 < 4) {
+        read_one(st, 1, 2 * g8, p1, q1, b1);
+        read_one(st, 1, 2 * g8 + 1, p1, q1, b1);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
     // stage st+1 is in LDS for every wave; every wave has read all of stage st
     wait_vm_lgkm0<(S - 2) * LPW>();
     barrier_only();
-    issue(st + S);
-    read_pair(st + 1, 0, p0, q0, b0);  // (past the last stage: a clamped copy, unused)
-    __builtin_amdgcn_sched_barrier(0);
-    mfma_pair(p1, q1, b1);
+#pragma unroll
+    for (int g8 = 0; g8 < NG; g8++) {
+      mfma_group(g8, p1, q1, b1);
+      if (g8 < 4) {  // (past the last stage: reads of a clamped copy, unused)
+        read_one(st + 1, 0, 2 * g8, p0, q0, b0);
+        read_one(st + 1, 0, 2 * g8 + 1, p0, q0, b0);
+      }
+      if (g8 >= 2) issue_one(st + S, g8 - 2);
+      __builtin_amdgcn_sched_barrier(0);
+    }
     asm volatile("" ::: "memory");
   }
   wait_vm_lgkm0<0>();
