@@ -4,6 +4,8 @@
   libglsgen.so  the synthetic-input generator (host C, OpenMP)
   libglsgen_dev.so  its device twin (HIP), for inputs generated in HBM
   tests/c_abi/gls_c_check  a C program using only include/gls.h (test)
+  libgls_phase.so  libgls.so with phase timestamps in the paired-block solve
+                   (measurement build, read by phase_timing.py)
 
 Run `python -m paper_1210_7325_amd.build` or call build_all().
 """
@@ -86,6 +88,28 @@ def build_gls(verbose: bool = False) -> str:
     return os.path.join(PKG, "libgls.so")
 
 
+def build_phase_timing() -> str:
+    """libgls.so's units with gls_trsm.hip replaced by trsm_phase_timing.hip
+    (the same kernels plus phase timestamps; a measurement build, not the
+    library).  Reuses the other units' objects of build_gls."""
+    os.makedirs(BUILD, exist_ok=True)
+    objs = []
+    for src in GLS_UNITS:
+        if src == "gls_trsm.hip":
+            src = "trsm_phase_timing.hip"
+            obj = os.path.join(BUILD, src + ".o")
+            _run([HIPCC, "-x", "hip", *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
+        else:
+            obj = os.path.join(BUILD, src + ".o")
+            if not os.path.exists(obj):
+                _run([HIPCC, "-x", "hip", *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
+        objs.append(obj)
+    tmp = os.path.join(PKG, "libgls_phase.so.tmp")
+    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp])
+    os.replace(tmp, os.path.join(PKG, "libgls_phase.so"))
+    return os.path.join(PKG, "libgls_phase.so")
+
+
 def build_gen() -> str:
     out = os.path.join(PKG, "libglsgen.so")
     cc = shutil.which("gcc") or "cc"
@@ -138,6 +162,7 @@ def build_all() -> None:
     build_gen()
     build_gen_dev()
     build_gls()
+    build_phase_timing()
     build_c_check()
     build_mfma_valu_bench()
 

@@ -3,6 +3,27 @@
 
 namespace gls {
 
+// Phase timestamps of k_trsm_pair, compiled only into the measurement build
+// (trsm_phase_timing.hip): thread 0 of each of the first PHASE_WGS
+// work-groups records the constant 100 MHz clock and the shader clock at
+// PHASE_POINTS points of each row-block pair.  Without GLS_PHASE_TIMING the
+// stamps compile to nothing.
+#ifdef GLS_PHASE_TIMING
+constexpr int PHASE_WGS = 256, PHASE_PAIRS = 64, PHASE_POINTS = 6;
+__device__ unsigned long long g_phase_rt[PHASE_WGS * PHASE_PAIRS * PHASE_POINTS];
+__device__ unsigned long long g_phase_cyc[PHASE_WGS * PHASE_PAIRS * PHASE_POINTS];
+#define PHASE_STAMP(pair, point)                                                              \
+  do {                                                                                        \
+    if (threadIdx.x == 0 && blockIdx.x < PHASE_WGS && (pair) < PHASE_PAIRS) {                 \
+      const size_t i_ = ((size_t)blockIdx.x * PHASE_PAIRS + (pair)) * PHASE_POINTS + (point); \
+      g_phase_rt[i_] = wall_clock64();                                                        \
+      g_phase_cyc[i_] = clock64();                                                            \
+    }                                                                                         \
+  } while (0)
+#else
+#define PHASE_STAMP(pair, point) ((void)0)
+#endif
+
 // ---------------------------------------------------------------------------
 // a2: blocked lower triangular solve  W = L^{-1} X  (the trsm of Alg. 5,
 // grouped over many right-hand sides as the paper prescribes)
@@ -59,7 +80,12 @@ __device__ __forceinline__ void gemm_staged_f64(const double* __restrict__ Lk,
   constexpr int NW = WR * WC;
   constexpr int CL = G * NT;           // chunks of L per stage
   constexpr int CPS = G * (NT + CTS);  // chunks per stage
-  constexpr int LPW_HI = (CPS + NW - 1) / NW, LPW_LO = CPS / NW;
+  constexpr int LPW = CPS / NW;        // copies per wave and stage
+  constexpr int NG = RT * CT;          // MFMA groups (output tiles) per half-stage
+  constexpr int NR = RT + CT;          // LDS reads per half-stage
+  constexpr int RPG = (NR + NG / 2 - 1) / (NG / 2);  // reads after each of the first NG/2 groups
+  static_assert(CPS % NW == 0 && NG >= 2 && LPW <= NG,
+                "every wave copies the same number of chunks, at most one after each group");
   double(*ring)[CPS * 128] = reinterpret_cast<double(*)[CPS * 128]>(ring_base);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x % 64;
   // (lets the compiler resolve which chunks a wave copies: no branches in
@@ -67,70 +93,67 @@ __device__ __forceinline__ void gemm_staged_f64(const double* __restrict__ Lk,
   __builtin_assume(wave >= 0 && wave < NW);
   const int wr = wave / WC, wc = wave % WC;
   const int nst = npairs / G;
-  const bool hi = LPW_HI == LPW_LO || wave < CPS % NW;  // this wave copies LPW_HI chunks
-  // this wave's copies of stage st (clamped to the last: the tail copies
-  // are never read) into its slot st % S (chunk c = wave + i NW)
-  auto issue = [&](int st) {
+  // copy i of this wave (chunk c = wave + i NW) of stage st (clamped to the
+  // last: the tail copies are never read) into slot st % S
+  auto issue_one = [&](int st, int i) {
     const int sl = st % S;
     st = st < nst ? st : nst - 1;
-#pragma unroll
-    for (int i = 0; i < LPW_HI; i++) {
-      const int c = wave + i * NW;
-      if (c < CPS) {
-        const double* src = c < CL ? Lk + ((size_t)st * CL + c) * 128 + lane * 2
-                                   : Wslab + ((size_t)st * G * CTS + (c - CL)) * 128 + lane * 2;
-        chunk_to_lds(src, &ring[sl][c * 128]);
-      }
-    }
+    const int c = wave + i * NW;
+    const double* src = c < CL ? Lk + ((size_t)st * CL + c) * 128 + lane * 2
+                               : Wslab + ((size_t)st * G * CTS + (c - CL)) * 128 + lane * 2;
+    chunk_to_lds(src, &ring[sl][c * 128]);
   };
-  auto read_pair = [&](int st, int g, d2 (&a)[RT], d2 (&b)[CT]) {
+  // operand fragment r of pair g of stage st: r < RT rows of L, then the W
+  // column tiles
+  auto read_one = [&](int st, int g, int r, d2 (&a)[RT], d2 (&b)[CT]) {
     const double* __restrict__ slot = ring[st % S];
-#pragma unroll
-    for (int rt = 0; rt < RT; rt++)
-      a[rt] = *reinterpret_cast<const d2*>(slot + (g * NT + wr * RT + rt) * 128 + lane * 2);
-#pragma unroll
-    for (int ct = 0; ct < CT; ct++)
-      b[ct] = *reinterpret_cast<const d2*>(slot + (CL + g * CTS + wc * CT + ct) * 128 + lane * 2);
+    if (r < RT)
+      a[r] = *reinterpret_cast<const d2*>(slot + (g * NT + wr * RT + r) * 128 + lane * 2);
+    else
+      b[r - RT] = *reinterpret_cast<const d2*>(slot + (CL + g * CTS + wc * CT + r - RT) * 128 + lane * 2);
   };
-  auto mfma_pair = [&](const d2 (&a)[RT], const d2 (&b)[CT]) {
-#pragma unroll
-    for (int rt = 0; rt < RT; rt++)
-#pragma unroll
-      for (int ct = 0; ct < CT; ct++) {
-        acc[rt][ct] = MFMA64(a[rt].x, b[ct].x, acc[rt][ct]);
-        acc[rt][ct] = MFMA64(a[rt].y, b[ct].y, acc[rt][ct]);
-      }
+  auto mfma_group = [&](int g8, const d2 (&a)[RT], const d2 (&b)[CT]) {
+    const int rt = g8 / CT, ct = g8 % CT;
+    acc[rt][ct] = MFMA64(a[rt].x, b[ct].x, acc[rt][ct]);
+    acc[rt][ct] = MFMA64(a[rt].y, b[ct].y, acc[rt][ct]);
   };
   // all S slots filled, stage 0 visible
 #pragma unroll
-  for (int st = 0; st < S; st++) issue(st);
-  if (hi)
-    wait_vm_lgkm0<(S - 1) * LPW_HI>();
-  else
-    wait_vm_lgkm0<(S - 1) * LPW_LO>();
+  for (int st = 0; st < S; st++)
+#pragma unroll
+    for (int i = 0; i < LPW; i++) issue_one(st, i);
+  wait_vm_lgkm0<(S - 1) * LPW>();
   barrier_only();
   d2 a0[RT], b0[CT], a1[RT], b1[CT];
-  read_pair(0, 0, a0, b0);
+#pragma unroll
+  for (int r = 0; r < NR; r++) read_one(0, 0, r, a0, b0);
+  // Each half-stage's MFMAs go out one output tile at a time, and the other
+  // instructions of the half sit between the tiles: the next half's LDS
+  // reads after the first NG/2 tiles, and after the barrier this wave's
+  // copies of stage st + S after the last LPW tiles (issued as a block
+  // before the MFMAs, they left the matrix pipe idle).
   for (int st = 0; st < nst; st++) {
-    // the first pair's reads, issued a pair of MFMAs ago, have landed; waiting
-    // here keeps the wait for them from also covering the reads issued next
     wait_lgkm0();
-    read_pair(st, 1, a1, b1);
-    // the reads go out before the MFMAs that hide them (the scheduler would
-    // otherwise sink them next to their use)
-    __builtin_amdgcn_sched_barrier(0);
-    mfma_pair(a0, b0);
-    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int g8 = 0; g8 < NG; g8++) {
+      mfma_group(g8, a0, b0);
+#pragma unroll
+      for (int r = g8 * RPG; r < (g8 + 1) * RPG; r++)
+        if (r < NR) read_one(st, 1, r, a1, b1);
+      __builtin_amdgcn_sched_barrier(0);
+    }
     // stage st+1 is in LDS for every wave; every wave has read all of stage st
-    if (hi)
-      wait_vm_lgkm0<(S - 2) * LPW_HI>();
-    else
-      wait_vm_lgkm0<(S - 2) * LPW_LO>();
+    wait_vm_lgkm0<(S - 2) * LPW>();
     barrier_only();
-    issue(st + S);
-    read_pair(st + 1, 0, a0, b0);  // (past the last stage: a clamped copy, unused)
-    __builtin_amdgcn_sched_barrier(0);
-    mfma_pair(a1, b1);
+#pragma unroll
+    for (int g8 = 0; g8 < NG; g8++) {
+      mfma_group(g8, a1, b1);
+#pragma unroll
+      for (int r = g8 * RPG; r < (g8 + 1) * RPG; r++)  // (past the last stage: reads of a clamped copy, unused)
+        if (r < NR) read_one(st + 1, 0, r, a0, b0);
+      if (g8 >= NG - LPW) issue_one(st + S, g8 - (NG - LPW));
+      __builtin_amdgcn_sched_barrier(0);
+    }
     asm volatile("" ::: "memory");
   }
   // the ring shares its LDS with the right-hand side staged next: the tail
@@ -565,6 +588,7 @@ __global__ __launch_bounds__(64 * PAIR_WR * PAIR_WC) void k_trsm_pair(const JobT
   const int Kmain = last_block_split(n, K, LAST_RW) ? K - 1 : K;
   for (int k = 0; k < Kmain; k += 2) {
     const bool two = k + 1 < Kmain;  // a lone last block: its partner's GEMM rows are discarded
+    PHASE_STAMP(k / 2, 0);
     d4 acc0[RT][CT], acc1[RT][CT];
 #pragma unroll
     for (int a = 0; a < RT; a++)
@@ -574,6 +598,7 @@ __global__ __launch_bounds__(64 * PAIR_WR * PAIR_WC) void k_trsm_pair(const JobT
     if (npairs > 0)
       gemm_staged_pair<C, WR, WC, S>(Lstrips + strip_offset(k), Lstrips + strip_offset(two ? k + 1 : k), Wslab,
                                      npairs, Rl, acc0, acc1);
+    PHASE_STAMP(k / 2, 1);
 
     TIn xv0[RT][CT][4], xv1[RT][CT][4];
     load_rhs<RT, CT>(X, ldx, n, ncols, (int64_t)k * NB + wr_rows, col_base, lane, xv0);
@@ -586,6 +611,7 @@ __global__ __launch_bounds__(64 * PAIR_WR * PAIR_WC) void k_trsm_pair(const JobT
     diag_step_dealt<CT, CTS>(LinvP, k, Rl, wr, wc_tile, lane, acc0);
     if (two) __syncthreads();
     store_w_dealt<CT, CTS>(Wslab, two ? Rl : nullptr, k, wr, wc_tile, lane, acc0);
+    PHASE_STAMP(k / 2, 2);
     if (two) {
       // block k+1's right-hand side, consumed after the L_{k+1,k} W_k
       // products, which hide its latency
@@ -624,6 +650,7 @@ __global__ __launch_bounds__(64 * PAIR_WR * PAIR_WC) void k_trsm_pair(const JobT
           }
         }
       }
+      PHASE_STAMP(k / 2, 3);
       // block k+1: R_{k+1} replaces W_k in LDS once every wave is done
       // reading it
       __syncthreads();
@@ -631,11 +658,13 @@ __global__ __launch_bounds__(64 * PAIR_WR * PAIR_WC) void k_trsm_pair(const JobT
       __syncthreads();
       diag_step_dealt<CT, CTS>(LinvP, k + 1, Rl, wr, wc_tile, lane, acc1);
       store_w_dealt<CT, CTS>(Wslab, nullptr, k + 1, wr, wc_tile, lane, acc1);
+      PHASE_STAMP(k / 2, 4);
     }
     // the W stores are visible to the work-group's next copies, and every
     // wave is done reading Rl before the next stage ring overwrites it
     __threadfence_block();
     __syncthreads();
+    PHASE_STAMP(k / 2, 5);
   }
 }
 

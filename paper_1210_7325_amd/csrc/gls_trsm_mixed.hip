@@ -78,69 +78,91 @@ __device__ __forceinline__ void gemm_staged(const float* __restrict__ Lk, const 
   constexpr int NW = WR * WC;
   constexpr int CL = G * NQB;          // chunks of L per stage
   constexpr int CPS = G * (NQB + CTS); // chunks per stage
-  constexpr int LPW_HI = (CPS + NW - 1) / NW, LPW_LO = CPS / NW;
+  constexpr int LPW = CPS / NW;        // copies per wave and stage
+  constexpr int NR = RT + CT;          // LDS reads per quad
+  constexpr int RPS = (NR + 2) / 3;    // reads placed after each of a quad's first three k-steps
+  static_assert(CPS % NW == 0 && 2 + LPW <= 4 * RT,
+                "every wave copies the same number of chunks, one after each k-step of the second quad "
+                "from the third on");
   float(*ring)[CPS * 256] = reinterpret_cast<float(*)[CPS * 256]>(ring_base);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x % 64;
   __builtin_assume(wave >= 0 && wave < NW);
   const int wr = wave / WC, wc = wave % WC;
   const int nst = nq / G;
-  const bool hi = LPW_HI == LPW_LO || wave < CPS % NW;  // this wave copies LPW_HI chunks
-  // this wave's copies of stage st (clamped to the last: the tail copies
-  // are never read) into its slot st % S (chunk c = wave + i NW)
-  auto issue = [&](int st) {
+  // copy i of this wave (chunk c = wave + i NW) of stage st (clamped to the
+  // last: the tail copies are never read) into slot st % S
+  auto issue_one = [&](int st, int i) {
     const int sl = st % S;
     st = st < nst ? st : nst - 1;
-#pragma unroll
-    for (int i = 0; i < LPW_HI; i++) {
-      const int c = wave + i * NW;
-      if (c < CPS) {
-        const float* src = c < CL ? Lk + ((size_t)st * CL + c) * 256 + lane * 4
-                                  : W32slab + ((size_t)st * G * CTS + (c - CL)) * 256 + lane * 4;
-        chunk_to_lds(src, &ring[sl][c * 256]);
-      }
-    }
+    const int c = wave + i * NW;
+    const float* src = c < CL ? Lk + ((size_t)st * CL + c) * 256 + lane * 4
+                              : W32slab + ((size_t)st * G * CTS + (c - CL)) * 256 + lane * 4;
+    chunk_to_lds(src, &ring[sl][c * 256]);
   };
-  auto read_quad = [&](int st, int g, f4 (&a)[RT], f4 (&b)[CT]) {
+  // operand fragment r of quad g of stage st: r < RT rows of L, then the W
+  // column tiles
+  auto read_one = [&](int st, int g, int r, f4 (&a)[RT], f4 (&b)[CT]) {
     const float* __restrict__ slot = ring[st % S];
-#pragma unroll
-    for (int rt = 0; rt < RT; rt++)
-      a[rt] = *reinterpret_cast<const f4*>(slot + (g * NQB + wr * RT + rt) * 256 + lane * 4);
-#pragma unroll
-    for (int ct = 0; ct < CT; ct++)
-      b[ct] = *reinterpret_cast<const f4*>(slot + (CL + g * CTS + wc * CT + ct) * 256 + lane * 4);
+    if (r < RT)
+      a[r] = *reinterpret_cast<const f4*>(slot + (g * NQB + wr * RT + r) * 256 + lane * 4);
+    else
+      b[r - RT] = *reinterpret_cast<const f4*>(slot + (CL + g * CTS + wc * CT + r - RT) * 256 + lane * 4);
   };
-  // the two quads of a stage form one chunk of the FP64 sum
   // all S slots filled, stage 0 visible
 #pragma unroll
-  for (int st = 0; st < S; st++) issue(st);
-  if (hi)
-    wait_vm_lgkm0<(S - 1) * LPW_HI>();
-  else
-    wait_vm_lgkm0<(S - 1) * LPW_LO>();
+  for (int st = 0; st < S; st++)
+#pragma unroll
+    for (int i = 0; i < LPW; i++) issue_one(st, i);
+  wait_vm_lgkm0<(S - 1) * LPW>();
   barrier_only();
   f4 a0[RT], b0[CT], a1[RT], b1[CT];
   f4 c0[RT][CT];
-  read_quad(0, 0, a0, b0);
+#pragma unroll
+  for (int r = 0; r < NR; r++) read_one(0, 0, r, a0, b0);
+  // The chains of both quads run one k-step at a time (the same chains as
+  // quad_chain and quad_chain_fold, the same bits), and the other
+  // instructions of each half-stage sit between the steps: the second
+  // quad's LDS reads in the first half; after the barrier, the next stage's
+  // first reads and this wave's copies of stage st + S.  Issued as a block
+  // before the MFMAs, they left the matrix pipe idle while both waves of a
+  // SIMD issued them.
   for (int st = 0; st < nst; st++) {
-    // the first quad's reads, issued a quad of MFMAs ago, have landed; waiting
-    // here keeps the wait for them from also covering the reads issued next
     wait_lgkm0();
-    read_quad(st, 1, a1, b1);
-    // the reads go out before the MFMAs that hide them, and the MFMAs before
-    // the wait and the barrier
-    __builtin_amdgcn_sched_barrier(0);
-    quad_chain<RT, CT>(a0, b0, c0);
-    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+#pragma unroll
+      for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+        for (int ct = 0; ct < CT; ct++)
+          c0[rt][ct] = MFMA32(a0[rt][q], b0[ct][q], q == 0 ? ((f4){0, 0, 0, 0}) : c0[rt][ct]);
+#pragma unroll
+      for (int r = q * RPS; r < (q + 1) * RPS; r++)
+        if (q < 3 && r < NR) read_one(st, 1, r, a1, b1);
+      __builtin_amdgcn_sched_barrier(0);
+    }
     // stage st+1 is in LDS for every wave; every wave has read all of stage st
-    if (hi)
-      wait_vm_lgkm0<(S - 2) * LPW_HI>();
-    else
-      wait_vm_lgkm0<(S - 2) * LPW_LO>();
+    wait_vm_lgkm0<(S - 2) * LPW>();
     barrier_only();
-    issue(st + S);
-    read_quad(st + 1, 0, a0, b0);  // (past the last stage: a clamped copy, unused)
-    __builtin_amdgcn_sched_barrier(0);
-    quad_chain_fold<RT, CT>(a1, b1, c0, acc);
+    // second quad and the fold into the FP64 sum, one tile row at a time
+#pragma unroll
+    for (int rt = 0; rt < RT; rt++) {
+      f4 x[CT];
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+#pragma unroll
+        for (int ct = 0; ct < CT; ct++) x[ct] = MFMA32(a1[rt][q], b1[ct][q], q == 0 ? ((f4){0, 0, 0, 0}) : x[ct]);
+        const int step = rt * 4 + q;
+#pragma unroll
+        for (int r = step * RPS; r < (step + 1) * RPS; r++)  // (past the last stage: reads of a clamped copy, unused)
+          if (step < 3 && r < NR) read_one(st + 1, 0, r, a0, b0);
+        if (step >= 2 && step < 2 + LPW) issue_one(st + S, step - 2);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+#pragma unroll
+      for (int ct = 0; ct < CT; ct++)
+#pragma unroll
+        for (int i = 0; i < 4; i++) acc[rt][ct][i] += (double)(c0[rt][ct][i] + x[ct][i]);
+    }
     asm volatile("" ::: "memory");
   }
   // the ring shares its LDS with the right-hand side staged next: the tail
