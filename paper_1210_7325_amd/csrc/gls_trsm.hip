@@ -453,9 +453,20 @@ __device__ __forceinline__ void gemm_staged_pair(const double* __restrict__ Lk0,
   barrier_only();
 }
 
+// A zero of each input type in device memory: the load address of elements
+// outside the matrix.
+__device__ const int8_t kZeroI8 = 0;
+__device__ const double kZeroF64 = 0.0;
+__device__ __forceinline__ const int8_t* zero_of(const int8_t*) { return &kZeroI8; }
+__device__ __forceinline__ const double* zero_of(const double*) { return &kZeroF64; }
+
 // The wave's RT x CT tiles of a row block's right-hand side (rows row0 +
 // 16 rt + lane/16 + 4 i of the block, columns col_base + 16 ct + lane%16),
-// as loaded: plain loads when the tile lies inside the matrix.
+// as loaded.  Both forms issue one load per element and wait for none: plain
+// loads when the tile lies inside the matrix, else loads whose address is
+// that of a zero for the elements outside (no branch per element, so the
+// wait counts agree where the two forms join and a later wait for another
+// load does not have to wait for all of these).
 template <int RT, int CT, typename TIn>
 __device__ __forceinline__ void load_rhs(const TIn* __restrict__ X, int64_t ldx, int64_t n, int64_t ncols,
                                          int64_t row0, int64_t col_base, int lane, TIn (&xv)[RT][CT][4]) {
@@ -469,6 +480,10 @@ __device__ __forceinline__ void load_rhs(const TIn* __restrict__ X, int64_t ldx,
         for (int i = 0; i < 4; i++) xv[rt][ct][i] = xc[rt * 16 + 4 * i];
     }
   } else {
+    // (global address space for both, so that these are global loads, not
+    // flat ones, which the LDS wait counter would count too)
+    typedef const __attribute__((address_space(1))) TIn* gptr;
+    const gptr gX = (gptr)X, zero = (gptr)zero_of(X);
 #pragma unroll
     for (int rt = 0; rt < RT; rt++)
 #pragma unroll
@@ -477,7 +492,7 @@ __device__ __forceinline__ void load_rhs(const TIn* __restrict__ X, int64_t ldx,
         for (int i = 0; i < 4; i++) {
           const int64_t row = row0 + rt * 16 + lane / 16 + 4 * i;
           const int64_t col = col_base + ct * 16 + lane % 16;
-          xv[rt][ct][i] = (row < n && col < ncols) ? X[col * ldx + row] : (TIn)0;
+          xv[rt][ct][i] = *((row < n && col < ncols) ? gX + col * ldx + row : zero);
         }
   }
 }
@@ -504,34 +519,70 @@ __device__ __forceinline__ void to_pair_layout(double* __restrict__ Rl, int wr_r
 
 // The diagonal step of k_trsm_pair with the row tiles dealt for balance:
 // 16-row tile t of inv(L_kk) R_k needs the first 2(t+1) k-step pairs (the
-// rest of its row of inv(L_kk) is zero), so wave row wr takes tiles wr and
-// NB/16 - 1 - wr (NB/8 + 2 pairs for every wave row, against up to 2 NB/8
-// for wave row WR - 1 when it holds the last two tiles).  Same products in
-// the same order per element as diag_step.
-template <int CT, int CTS>
-__device__ __forceinline__ void diag_step_dealt(const double* __restrict__ LinvP, int k,
-                                                const double* __restrict__ Rl, int wr, int wc_tile, int lane,
-                                                d4 (&w)[2][CT]) {
-  constexpr int NT = NB / 16;
+// rest of its row of inv(L_kk) is zero), so wave row W takes tiles W and
+// NB/16 - 1 - W: NB/8 + 2 = 18 steps for every wave row (against up to
+// 2 NB/8 for wave row WR - 1 when it holds the last two tiles).  Same
+// products in the same order per element as diag_step.
+//
+// The wave row is a template parameter (the caller switches on it), so the
+// 18 steps unroll with static registers: the inv(L_kk) fragments are loaded
+// DIAG_PF steps ahead (the first ones by diag_prefetch, before R_k is
+// staged) and the R_k fragments one step ahead, and no step waits for a
+// load it has just issued (with a run-time trip count every step waited
+// for its own inv(L_kk) load from L2 and its LDS reads).
+constexpr int DIAG_PF = 4;
+
+template <int W>
+__device__ __forceinline__ const double* diag_a_ptr(const double* __restrict__ Li, int s) {
+  constexpr int NT = NB / 16, NA = 2 * (W + 1);
+  return s < NA ? Li + ((size_t)s * NT + W) * 128 : Li + ((size_t)(s - NA) * NT + (NT - 1 - W)) * 128;
+}
+
+template <int W>
+__device__ __forceinline__ void diag_prefetch(const double* __restrict__ LinvP, int k, int lane, d2 (&pa)[DIAG_PF]) {
   const double* __restrict__ Li = LinvP + (size_t)k * NB * NB + lane * 2;
 #pragma unroll
-  for (int h = 0; h < 2; h++) {
-    const int t = h == 0 ? wr : NT - 1 - wr;
+  for (int s = 0; s < DIAG_PF; s++) pa[s] = *reinterpret_cast<const d2*>(diag_a_ptr<W>(Li, s));
+}
+
+template <int CT, int CTS, int W>
+__device__ __forceinline__ void diag_step_dealt(const double* __restrict__ LinvP, int k,
+                                                const double* Rl, int wc_tile, int lane,
+                                                const d2 (&pa)[DIAG_PF], d4 (&w)[2][CT]) {
+  constexpr int NT = NB / 16, NA = 2 * (W + 1), NS = NA + 2 * (NT - W);
+  static_assert(NS > DIAG_PF, "prefetch depth");
+  const double* __restrict__ Li = LinvP + (size_t)k * NB * NB + lane * 2;
+  auto read_b = [&](int s, d2 (&b)[CT]) {
+    const int kp = s < NA ? s : s - NA;
 #pragma unroll
-    for (int b = 0; b < CT; b++) w[h][b] = (d4){0, 0, 0, 0};
-    const int kp_end = 2 * (t + 1);
-    for (int kp = 0; kp < kp_end; kp++) {
-      const d2 a = *reinterpret_cast<const d2*>(Li + ((size_t)kp * NT + t) * 128);
-      d2 b[CT];
+    for (int ct = 0; ct < CT; ct++)
+      b[ct] = *reinterpret_cast<const d2*>(&Rl[((size_t)kp * CTS + wc_tile + ct) * 128 + lane * 2]);
+  };
+  d2 a[NS], b[2][CT];
 #pragma unroll
-      for (int ct = 0; ct < CT; ct++)
-        b[ct] = *reinterpret_cast<const d2*>(&Rl[((size_t)kp * CTS + wc_tile + ct) * 128 + lane * 2]);
+  for (int s = 0; s < DIAG_PF; s++) a[s] = pa[s];
 #pragma unroll
-      for (int ct = 0; ct < CT; ct++) {
-        w[h][ct] = MFMA64(a.x, b[ct].x, w[h][ct]);
-        w[h][ct] = MFMA64(a.y, b[ct].y, w[h][ct]);
-      }
+  for (int h = 0; h < 2; h++)
+#pragma unroll
+    for (int ct = 0; ct < CT; ct++) w[h][ct] = (d4){0, 0, 0, 0};
+  read_b(0, b[0]);
+#pragma unroll
+  for (int s = 0; s < NS; s++) {
+    if (s + DIAG_PF < NS) a[s + DIAG_PF] = *reinterpret_cast<const d2*>(diag_a_ptr<W>(Li, s + DIAG_PF));
+    if (s + 1 < NS) read_b(s + 1, b[(s + 1) % 2]);
+    const int h = s < NA ? 0 : 1;
+#pragma unroll
+    for (int ct = 0; ct < CT; ct++) {
+      w[h][ct] = MFMA64(a[s].x, b[s % 2][ct].x, w[h][ct]);
+      w[h][ct] = MFMA64(a[s].y, b[s % 2][ct].y, w[h][ct]);
     }
+    // the loads first, then the MFMAs (left alone, the scheduler sinks the
+    // loads below the MFMAs to shorten their registers' lives, and every
+    // step then waits for its own reads)
+    if (s + DIAG_PF < NS) __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+    if (s + 1 < NS) __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
+    __builtin_amdgcn_sched_group_barrier(0x008, 2 * CT, 0);
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
@@ -550,11 +601,28 @@ __device__ __forceinline__ void store_w_dealt(double* __restrict__ Wslab, double
 #pragma unroll
       for (int i = 0; i < 4; i += 2) {
         const d2 v = (d2){w[h][ct][i], w[h][ct][i + 1]};
-        *reinterpret_cast<d2*>(Wslab + ((size_t)((ks0 + i) / 2) * CTS + wc_tile + ct) * 128 + lane * 2) = v;
-        if (Wl) *reinterpret_cast<d2*>(&Wl[((size_t)((4 * t + i) / 2) * CTS + wc_tile + ct) * 128 + lane * 2]) = v;
+        // (typed global and LDS stores: generic ones would compile to flat
+        // stores, which every later LDS wait would have to wait for too)
+        *(__attribute__((address_space(1))) d2*)(Wslab + ((size_t)((ks0 + i) / 2) * CTS + wc_tile + ct) * 128 +
+                                                  lane * 2) = v;
+        if (Wl) *(__attribute__((address_space(3))) d2*)(&Wl[((size_t)((4 * t + i) / 2) * CTS + wc_tile + ct) * 128 +
+                                                           lane * 2]) = v;
       }
   }
 }
+
+// Runs STMT with the constant WROW = this wave's row (wave-uniform: a
+// scalar branch, no divergence).
+#define DIAG_BY_ROW(STMT)                        \
+  do {                                           \
+    static_assert(PAIR_WR == 4, "four wave rows"); \
+    switch (wr) {                                \
+      case 0: { constexpr int WROW = 0; STMT; } break; \
+      case 1: { constexpr int WROW = 1; STMT; } break; \
+      case 2: { constexpr int WROW = 2; STMT; } break; \
+      default: { constexpr int WROW = 3; STMT; } break; \
+    }                                            \
+  } while (0)
 
 template <int C, typename TIn>
 __global__ __launch_bounds__(64 * PAIR_WR * PAIR_WC) void k_trsm_pair(const JobTable tab) {
@@ -600,63 +668,78 @@ __global__ __launch_bounds__(64 * PAIR_WR * PAIR_WC) void k_trsm_pair(const JobT
                                      npairs, Rl, acc0, acc1);
     PHASE_STAMP(k / 2, 1);
 
+    // int8 right-hand sides: both blocks' at once, so that block k+1's
+    // arrives with block k's, which the staging below waits for anyway
+    // (issued later, any wait for a load issued after them would wait for
+    // them too; unused for a lone last block).  FP64 ones (8 times the
+    // registers) are loaded one block at a time.
+    constexpr bool kEarly = sizeof(TIn) == 1;
     TIn xv0[RT][CT][4], xv1[RT][CT][4];
     load_rhs<RT, CT>(X, ldx, n, ncols, (int64_t)k * NB + wr_rows, col_base, lane, xv0);
+    if (kEarly) load_rhs<RT, CT>(X, ldx, n, ncols, (int64_t)(k + 1) * NB + wr_rows, col_base, lane, xv1);
+    d2 pa[DIAG_PF];
+    DIAG_BY_ROW(diag_prefetch<WROW>(LinvP, k, lane, pa));
 
     // block k: R_k to LDS, W_k = inv(L_kk) R_k, stored (and, when block
     // k+1 follows, put in LDS in place of R_k once every wave is done
     // reading R_k)
     to_pair_layout<RT, CT, CTS>(Rl, wr_rows, wc_tile, lane, xv0, acc0, true);
     __syncthreads();
-    diag_step_dealt<CT, CTS>(LinvP, k, Rl, wr, wc_tile, lane, acc0);
+    DIAG_BY_ROW((diag_step_dealt<CT, CTS, WROW>(LinvP, k, Rl, wc_tile, lane, pa, acc0)));
     if (two) __syncthreads();
     store_w_dealt<CT, CTS>(Wslab, two ? Rl : nullptr, k, wr, wc_tile, lane, acc0);
     PHASE_STAMP(k / 2, 2);
     if (two) {
-      // block k+1's right-hand side, consumed after the L_{k+1,k} W_k
-      // products, which hide its latency
-      load_rhs<RT, CT>(X, ldx, n, ncols, (int64_t)(k + 1) * NB + wr_rows, col_base, lane, xv1);
-      __syncthreads();
-      // acc_{k+1} += L_{k+1,k} W_k: the last NPB pairs of strip k+1, a
-      // register ring of D pairs
+      // acc_{k+1} += L_{k+1,k} W_k: the last NPB pairs of strip k+1 (from
+      // global memory, D pairs ahead) against W_k (from LDS, one pair ahead)
       constexpr int D = 4;
       const double* __restrict__ Ls =
           Lstrips + strip_offset(k + 1) + (size_t)k * NPB * (NB / 16) * 128 + (size_t)(wr * RT) * 128 + lane * 2;
-      d2 a[D][RT];
+      d2 a[NPB][RT], b[2][CT];
 #pragma unroll
       for (int s = 0; s < D; s++)
 #pragma unroll
         for (int rt = 0; rt < RT; rt++) a[s][rt] = *reinterpret_cast<const d2*>(Ls + ((size_t)s * (NB / 16) + rt) * 128);
+      if (!kEarly) {
+        asm volatile("" ::: "memory");  // (after the first pairs of L, so that waiting for those does not wait for it)
+        load_rhs<RT, CT>(X, ldx, n, ncols, (int64_t)(k + 1) * NB + wr_rows, col_base, lane, xv1);
+      }
+      __syncthreads();
+      auto read_b = [&](int kp, d2 (&bb)[CT]) {
 #pragma unroll
-      for (int kp0 = 0; kp0 < NPB; kp0 += D) {
+        for (int ct = 0; ct < CT; ct++)
+          bb[ct] = *reinterpret_cast<const d2*>(&Rl[((size_t)kp * CTS + wc_tile + ct) * 128 + lane * 2]);
+      };
+      read_b(0, b[0]);
 #pragma unroll
-        for (int s = 0; s < D; s++) {
-          const int kp = kp0 + s;
-          d2 b[CT];
-#pragma unroll
-          for (int ct = 0; ct < CT; ct++)
-            b[ct] = *reinterpret_cast<const d2*>(&Rl[((size_t)kp * CTS + wc_tile + ct) * 128 + lane * 2]);
+      for (int kp = 0; kp < NPB; kp++) {
+        if (kp + D < NPB) {
 #pragma unroll
           for (int rt = 0; rt < RT; rt++)
-#pragma unroll
-            for (int ct = 0; ct < CT; ct++) {
-              acc1[rt][ct] = MFMA64(a[s][rt].x, b[ct].x, acc1[rt][ct]);
-              acc1[rt][ct] = MFMA64(a[s][rt].y, b[ct].y, acc1[rt][ct]);
-            }
-          if (kp + D < NPB) {
-#pragma unroll
-            for (int rt = 0; rt < RT; rt++)
-              a[s][rt] = *reinterpret_cast<const d2*>(Ls + ((size_t)(kp + D) * (NB / 16) + rt) * 128);
-          }
+            a[kp + D][rt] = *reinterpret_cast<const d2*>(Ls + ((size_t)(kp + D) * (NB / 16) + rt) * 128);
         }
+        if (kp + 1 < NPB) read_b(kp + 1, b[(kp + 1) % 2]);
+#pragma unroll
+        for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+          for (int ct = 0; ct < CT; ct++) {
+            acc1[rt][ct] = MFMA64(a[kp][rt].x, b[kp % 2][ct].x, acc1[rt][ct]);
+            acc1[rt][ct] = MFMA64(a[kp][rt].y, b[kp % 2][ct].y, acc1[rt][ct]);
+          }
+        // the loads first, then the MFMAs (as in diag_step_dealt)
+        if (kp + D < NPB) __builtin_amdgcn_sched_group_barrier(0x020, RT, 0);
+        if (kp + 1 < NPB) __builtin_amdgcn_sched_group_barrier(0x100, CT, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, 2 * RT * CT, 0);
+        __builtin_amdgcn_sched_barrier(0);
       }
       PHASE_STAMP(k / 2, 3);
       // block k+1: R_{k+1} replaces W_k in LDS once every wave is done
       // reading it
+      DIAG_BY_ROW(diag_prefetch<WROW>(LinvP, k + 1, lane, pa));
       __syncthreads();
       to_pair_layout<RT, CT, CTS>(Rl, wr_rows, wc_tile, lane, xv1, acc1, true);
       __syncthreads();
-      diag_step_dealt<CT, CTS>(LinvP, k + 1, Rl, wr, wc_tile, lane, acc1);
+      DIAG_BY_ROW((diag_step_dealt<CT, CTS, WROW>(LinvP, k + 1, Rl, wc_tile, lane, pa, acc1)));
       store_w_dealt<CT, CTS>(Wslab, nullptr, k + 1, wr, wc_tile, lane, acc1);
       PHASE_STAMP(k / 2, 4);
     }

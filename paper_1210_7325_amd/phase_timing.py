@@ -33,12 +33,13 @@ def main() -> None:
     ap.add_argument("--n", type=int, default=10_000)
     ap.add_argument("--cols", type=int, default=32_768, help="right-hand sides (one launch: <= 128 x CUs)")
     ap.add_argument("--runs", type=int, default=3, help="launches; the last one's stamps are read")
+    ap.add_argument("--lib", default=None, help="another build of libgls_phase.so (for comparisons)")
     args = ap.parse_args()
 
     import torch
     from paper_1210_7325_amd import datagen as dg
     from paper_1210_7325_amd import gls
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgls_phase.so")
+    path = args.lib or os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgls_phase.so")
     if not os.path.exists(path):
         raise ImportError(f"{path} is not built; run python -m paper_1210_7325_amd.build")
     gls.LIB_PATH = path
