@@ -166,6 +166,96 @@ __device__ __forceinline__ void mfma_dots(LoadA loadA, const double* __restrict_
   }
 }
 
+// The same products for p_R = 1 and ldf <= VD_LDF on FP64 FMAs, straight
+// into dots: lane (r, cl) of tile ct keeps its column's sums over its rows
+// (rows 8o + r and 8o + 4 + r of the wave's octets o) with the ldf columns
+// of F and with itself (the 1 x 1 Gram), then the four lanes of a column
+// add theirs (lanes r = 0..3, pairs first) and the waves theirs, in wave
+// order.  An MFMA here would compute a 16 x 16 tile of which 4 columns (and,
+// for the Gram, the diagonal) are used: on the FMAs the products take a
+// sixth of the cycles, and the kernel is left to the memory stream.  Every
+// sum runs over the rows in an order fixed by the row index alone.
+constexpr int VD_LDF = 4;
+
+template <class LoadA>
+__device__ __forceinline__ void valu_dots(LoadA loadA, const double* __restrict__ F, int ldf, int64_t noct,
+                                          int wave, int lane, double* __restrict__ red,
+                                          double (*dots)[AS_DOTS]) {
+  constexpr int E = VD_LDF + 1;  // F columns, then the squared norm
+  const int r = lane / 16, cl = lane % 16;
+  double part[4][E];
+#pragma unroll
+  for (int ct = 0; ct < 4; ct++)
+#pragma unroll
+    for (int e = 0; e < E; e++) part[ct][e] = 0.0;
+  constexpr int DEPTH = 2;
+  d2 av[DEPTH][4];
+  double f0[DEPTH][VD_LDF], f1[DEPTH][VD_LDF];
+  // (F's columns past ldf are read at column ldf - 1: those sums are never used)
+  auto fetch = [&](int64_t o, d2 (&a)[4], double (&g0)[VD_LDF], double (&g1)[VD_LDF])
+      __attribute__((always_inline)) {
+#pragma unroll
+    for (int ct = 0; ct < 4; ct++) a[ct] = loadA(ct, o);
+    const double* __restrict__ p0 = F + (8 * o + r) * ldf;
+    const double* __restrict__ p1 = p0 + 4 * ldf;
+#pragma unroll
+    for (int e = 0; e < VD_LDF; e++) {
+      g0[e] = p0[e < ldf ? e : ldf - 1];
+      g1[e] = p1[e < ldf ? e : ldf - 1];
+    }
+  };
+  auto clamp = [&](int64_t o) { return o < noct ? o : noct - 1; };
+  auto products = [&](int st) __attribute__((always_inline)) {
+#pragma unroll
+    for (int ct = 0; ct < 4; ct++) {
+#pragma unroll
+      for (int e = 0; e < VD_LDF; e++) {
+        part[ct][e] = fma(av[st][ct].x, f0[st][e], part[ct][e]);
+        part[ct][e] = fma(av[st][ct].y, f1[st][e], part[ct][e]);
+      }
+      part[ct][VD_LDF] = fma(av[st][ct].x, av[st][ct].x, part[ct][VD_LDF]);
+      part[ct][VD_LDF] = fma(av[st][ct].y, av[st][ct].y, part[ct][VD_LDF]);
+    }
+  };
+#pragma unroll
+  for (int st = 0; st < DEPTH; st++) fetch(clamp(wave + 8 * st), av[st], f0[st], f1[st]);
+  // whole rounds of DEPTH octets without a branch (so that each wait is for
+  // the stage it feeds, not for every load in flight), then the last round
+  int64_t o0 = wave;
+  for (; o0 + 8 * (DEPTH - 1) < noct; o0 += 8 * DEPTH) {
+#pragma unroll
+    for (int st = 0; st < DEPTH; st++) {
+      products(st);
+      __builtin_amdgcn_sched_barrier(0);
+      fetch(clamp(o0 + 8 * (st + DEPTH)), av[st], f0[st], f1[st]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+#pragma unroll
+  for (int st = 0; st < DEPTH; st++)
+    if (o0 + 8 * st < noct) products(st);
+  // the four lanes of each column: (r0 + r1) + (r2 + r3) on every lane
+  // (a + b is b + a to the bit); lane r = 0 then holds the wave's sum
+#pragma unroll
+  for (int ct = 0; ct < 4; ct++)
+#pragma unroll
+    for (int e = 0; e < E; e++) {
+      double v = part[ct][e];
+      v += __shfl_xor(v, 16);
+      v += __shfl_xor(v, 32);
+      if (r == 0) red[(wave * AS_COLS + 16 * ct + cl) * E + e] = v;
+    }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < AS_COLS * E; idx += 64 * AS_WAVES) {
+    const int c = idx / E, e = idx % E;
+    double v = 0.0;
+    for (int w = 0; w < AS_WAVES; w++) v += red[(w * AS_COLS + c) * E + e];
+    if (e < ldf) dots[c][e] = v;
+    if (e == VD_LDF) dots[c][ldf] = v;
+  }
+  __syncthreads();
+}
+
 // Fixed-order sum over the waves of one 16-wide slice of the products:
 // slice et of every tile lands in red, then dots[c][16 et + e] (e < elim)
 // or, for the Gram slice (gram_pR > 0), dots[c][base + q] = G[c][c0 + q]
@@ -214,7 +304,7 @@ __device__ __forceinline__ void reduce_slice(const d4 (&acc)[4][ET + 1], int et,
 //   r = c' - S' b0,  d = (G G^T)^{-1} r,  b' = b0 + d,
 // then b_L[icol] -= s^T b'_R undoes the centering.
 template <bool REFINE, int ET>
-__global__ __launch_bounds__(64 * AS_WAVES, ET == 1 ? 4 : 2) void k_assemble_solve(const AsmTable tab) {
+__global__ __launch_bounds__(64 * AS_WAVES, ET <= 1 ? 4 : 2) void k_assemble_solve(const AsmTable tab) {
   __shared__ double red[AS_WAVES][AS_RED_COLS][17];
   __shared__ double dots[AS_COLS][AS_DOTS];
 
@@ -246,11 +336,17 @@ __global__ __launch_bounds__(64 * AS_WAVES, ET == 1 ? 4 : 2) void k_assemble_sol
   auto loadA = [&](int ct, int64_t o) __attribute__((always_inline)) -> d2 {
     return *reinterpret_cast<const d2*>(W + base[ct] + (size_t)o * ostride);
   };
-  d4 acc[4][ET + 1];
-  mfma_dots<ET, true>(loadA, J.F, ldf, (J.n + 7) / 8, wave, lane, acc);
+  if constexpr (ET == 0) {
+    // (every job of this launch has p_R = 1 and ldf <= VD_LDF)
+    static_assert(AS_WAVES * AS_COLS * (VD_LDF + 1) <= AS_WAVES * AS_RED_COLS * 17, "red holds the sums");
+    valu_dots(loadA, J.F, ldf, (J.n + 7) / 8, wave, lane, &red[0][0][0], dots);
+  } else {
+    d4 acc[4][ET + 1];
+    mfma_dots<ET, true>(loadA, J.F, ldf, (J.n + 7) / 8, wave, lane, acc);
 #pragma unroll
-  for (int et = 0; et < ET; et++) reduce_slice<ET>(acc, et, wave, lane, red, dots, ldf, 0, 0);
-  reduce_slice<ET>(acc, ET, wave, lane, red, dots, 0, ldf, pR);
+    for (int et = 0; et < ET; et++) reduce_slice<ET>(acc, et, wave, lane, red, dots, ldf, 0, 0);
+    reduce_slice<ET>(acc, ET, wave, lane, red, dots, 0, ldf, pR);
+  }
 
   // one wavefront per problem
   for (int g = wave; g < ng; g += AS_WAVES) {
@@ -446,10 +542,38 @@ __global__ __launch_bounds__(256) void k_colsum(const double* __restrict__ Z, in
 }
 
 
-hipError_t launch_assemble_solve(const AsmTable& tab, int64_t ngroups, bool refine, hipStream_t st) {
+hipError_t launch_assemble_solve(const AsmTable& tab_in, int64_t ngroups, bool refine, hipStream_t st) {
+  // The jobs with one genotype column per problem and ldf <= VD_LDF go to
+  // the FMA form (ET = 0), the others to the MFMA form, each in a launch of
+  // its own: a job takes the same form whatever the other jobs of the call,
+  // so its results do not depend on them.
+  AsmTable fma_tab, tab;
+  fma_tab.njobs = tab.njobs = 0;
+  int64_t fma_groups = 0, groups = 0;
+  for (int i = 0; i < tab_in.njobs; i++) {
+    AsmDesc d = tab_in.j[i];
+    const int64_t per_group = (AS_GROUP_COLS / 16) * (16 / d.pR);
+    const int64_t ng = (d.nsnp + per_group - 1) / per_group;
+    if (d.pR == 1 && d.pL + d.t <= VD_LDF) {
+      d.grp0 = fma_groups;
+      fma_tab.j[fma_tab.njobs++] = d;
+      fma_groups += ng;
+    } else {
+      d.grp0 = groups;
+      tab.j[tab.njobs++] = d;
+      groups += ng;
+    }
+  }
+  if (fma_groups + groups != ngroups) return hipErrorInvalidValue;
+  const unsigned nt = 64 * AS_WAVES;
+  if (fma_groups > 0) {
+    if (refine) k_assemble_solve<true, 0><<<(unsigned)fma_groups, nt, 0, st>>>(fma_tab);
+    else k_assemble_solve<false, 0><<<(unsigned)fma_groups, nt, 0, st>>>(fma_tab);
+  }
+  if (groups == 0) return hipGetLastError();
   int w = 1;  // widest F = [W_L | ytil] of the table: one or two 16-column tiles
   for (int i = 0; i < tab.njobs; i++) w = std::max(w, tab.j[i].pL + tab.j[i].t);
-  const unsigned g = (unsigned)ngroups, nt = 64 * AS_WAVES;
+  const unsigned g = (unsigned)groups;
   if (w <= 16) {
     if (refine) k_assemble_solve<true, 1><<<g, nt, 0, st>>>(tab);
     else k_assemble_solve<false, 1><<<g, nt, 0, st>>>(tab);
