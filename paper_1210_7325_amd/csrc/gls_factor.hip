@@ -22,115 +22,93 @@ __global__ void k_copy_pad(const double* __restrict__ M, int64_t ldm, int64_t n,
   }
 }
 
-// Unblocked Cholesky of the diagonal block k, then its inverse, with the
-// block held in registers: thread t owns rows r + 16a and columns c + 16b
-// (r = t % 16, c = t / 16, a, b < 8) of the 128 x 128 block.
-//   factor, step j:  the owners of column j publish it (LDS, double
-//     buffered), every thread forms L[.][j] = A[.][j] / sqrt(A[j][j]) for
-//     the rows and columns it owns (reciprocal multiply, as LAPACK's
-//     unblocked potf2) and applies the rank-1 update to its trailing part;
-//   inverse, step j (X = inv(L) by row elimination of L X = I): the owners
-//     of row j scale it by 1 / L[j][j] and publish it; every thread subtracts
-//     L[i][j] X[j][.] from its rows i > j.
-// The steps run in 8 groups of 16 (template parameter JB = j / 16), so each
-// group touches only the register tiles it can change, with static indices.
-// One barrier per step.  Writes L_kk into A and into Ldiag[k], inv(L_kk)
-// into Linv[k] (NB x NB column-major, lower).  A non-positive or non-finite
-// pivot of a real row sets *info (order of the failing leading minor) and
-// stops the process: every later kernel sees *info != 0 and returns at once.
-__device__ __forceinline__ int tri_off(int j) { return j * NB - j * (j - 1) / 2; }
+// Cholesky of the diagonal block k and its inverse, blocked by 16 columns
+// with the block in LDS (column-major, leading dimension SLD).
+//   factor, panel p (columns c0 = 16p ..): wave 0 factors the panel (rows
+//     c0 .. NB-1, 16 columns) in registers, lane l holding rows c0 + l and
+//     c0 + l + 64: per column the pivot and the column of L come from
+//     v_readlane broadcasts (no barrier), L[i][j] = A[i][j] * (1 / sqrt(A[j][j]))
+//     (reciprocal multiply, as LAPACK's unblocked potf2), then the rank-1
+//     update of the panel's later columns; then all four waves subtract
+//     L21 L21^T from the trailing lower tiles on FP64 MFMA (16 x 16 tiles,
+//     four k-steps each).  Two barriers per panel instead of one per column.
+//   inverse X = inv(L), in packed lower storage: the diagonal 16 x 16 blocks
+//     by forward substitution (one lane per column, X_pp e_j), then block
+//     column j of X (two block columns per wave, j and 7 - j, so that every
+//     wave has 7 blocks): X_ij = -X_ii sum_{m=j}^{i-1} L_im X_mj for
+//     i = j+1 .., both products on FP64 MFMA.
+// Writes L_kk into A and into Ldiag[k], inv(L_kk) into Linv[k] (NB x NB
+// column-major, lower, zeros above).  A non-positive or non-finite pivot of a
+// real row sets *info (order of the failing leading minor) and stops the
+// process: every later kernel sees *info != 0 and returns at once.
+constexpr int SLD = NB + 1;                   // padded leading dimension of the block in LDS
+__device__ __forceinline__ int pk(int r, int c) { return c * NB - c * (c - 1) / 2 + (r - c); }  // packed lower
+constexpr int PK = NB * (NB + 1) / 2;         // packed lower triangle
 
-struct Potf2Ctx {
-  double (*buf)[NB];   // LDS, two buffers of one column or row
-  double* Lp;          // LDS, L by columns, lower triangle packed
-  int r, c, t;
-  int64_t o, n;
-  int fail;
-};
-
-template <int JB>
-__device__ __forceinline__ bool potf2_group(double (&T)[8][8], Potf2Ctx& x) {
-  const int r = x.r, c = x.c;
-#pragma unroll 1
-  for (int jj = 0; jj < 16; jj++) {
-    const int j = 16 * JB + jj;
-    double* col = x.buf[j & 1];
-    if (c == jj) {
+// wave 0: factor the panel of columns c0 .. c0+15 (rows c0 .. NB-1) of S in
+// place; returns the failing pivot's code (0 if none)
+__device__ __forceinline__ int panel_factor(double* __restrict__ S, int c0, int lane, int64_t o, int64_t n) {
+  double v[2][16];
 #pragma unroll
-      for (int a = JB; a < 8; a++)
-        if (a > JB || r >= jj) col[r + 16 * a] = T[a][JB];
-    }
-    __syncthreads();
-    const double d = col[j];
-    if (!(d > 0.0) || !(d < INFINITY)) {
-      x.fail = (x.o + j < x.n) ? (int)(x.o + j + 1) : -1;
-      return false;
-    }
+  for (int h = 0; h < 2; h++) {
+    const int row = c0 + lane + 64 * h;
+#pragma unroll
+    for (int q = 0; q < 16; q++) v[h][q] = row < NB ? S[(c0 + q) * SLD + row] : 0.0;
+  }
+#pragma unroll
+  for (int jj = 0; jj < 16; jj++) {
+    const double d = bcast_lane(v[0][jj], jj);   // pivot A[c0+jj][c0+jj]: lane jj, first row set
+    if (!(d > 0.0) || !(d < INFINITY)) return (o + c0 + jj < n) ? (int)(o + c0 + jj + 1) : (int)(o + 1);
     const double g = sqrt(d), rg = 1.0 / g;
-    double li[8], ll[8];   // L[i][j] of the owned rows, L[l][j] of the owned columns (0 if <= j)
 #pragma unroll
-    for (int a = JB; a < 8; a++) li[a] = (a > JB || r > jj) ? col[r + 16 * a] * rg : 0.0;
-#pragma unroll
-    for (int b = JB; b < 8; b++) ll[b] = (b > JB || c > jj) ? col[c + 16 * b] * rg : 0.0;
-    if (x.t < NB && x.t >= j) x.Lp[tri_off(j) + x.t - j] = x.t == j ? g : col[x.t] * rg;
-    if (c == jj) {
-#pragma unroll
-      for (int a = JB; a < 8; a++) {
-        if (a == JB && r == jj) T[a][JB] = g;
-        else if (a > JB || r > jj) T[a][JB] = li[a];
-      }
+    for (int h = 0; h < 2; h++) {
+      const int row = c0 + lane + 64 * h;
+      v[h][jj] = row > c0 + jj ? v[h][jj] * rg : (row == c0 + jj ? g : 0.0);
     }
-    // rank-1 update of the trailing tiles (a >= b >= JB); li, ll vanish
-    // outside rows and columns > j, and the strict upper part is not used
+    // L[c0+jj'][jj] of the panel's later columns (lanes jj', first row set);
+    // the entries above the diagonal this touches are never read
 #pragma unroll
-    for (int b = JB; b < 8; b++)
+    for (int q = jj + 1; q < 16; q++) {
+      const double lq = bcast_lane(v[0][jj], q);
 #pragma unroll
-      for (int a = b; a < 8; a++) T[a][b] -= li[a] * ll[b];
-  }
-  return true;
-}
-
-template <int JB>
-__device__ __forceinline__ void trtri_group(double (&T)[8][8], Potf2Ctx& x) {
-  const int r = x.r, c = x.c;
-#pragma unroll 1
-  for (int jj = 0; jj < 16; jj++) {
-    const int j = 16 * JB + jj;
-    double* row = x.buf[j & 1];
-    const double djj = 1.0 / x.Lp[tri_off(j)];
-    if (r == jj) {
-#pragma unroll
-      for (int b = 0; b <= JB; b++) {
-        if (b < JB || c <= jj) {
-          T[JB][b] *= djj;
-          row[c + 16 * b] = T[JB][b];
-        }
-      }
+      for (int h = 0; h < 2; h++) v[h][q] = fma(-v[h][jj], lq, v[h][q]);
     }
-    __syncthreads();
-    double li[8], xj[8];
-#pragma unroll
-    for (int a = JB; a < 8; a++)
-      li[a] = (a > JB || r > jj) ? x.Lp[tri_off(j) + r + 16 * a - j] : 0.0;
-#pragma unroll
-    for (int b = 0; b <= JB; b++) xj[b] = (b < JB || c <= jj) ? row[c + 16 * b] : 0.0;
-#pragma unroll
-    for (int a = JB; a < 8; a++)
-#pragma unroll
-      for (int b = 0; b <= JB; b++) T[a][b] -= li[a] * xj[b];
   }
+#pragma unroll
+  for (int h = 0; h < 2; h++) {
+    const int row = c0 + lane + 64 * h;
+    if (row < NB) {
+#pragma unroll
+      for (int q = 0; q < 16; q++) S[(c0 + q) * SLD + row] = row >= c0 + q ? v[h][q] : 0.0;
+    }
+  }
+  return 0;
 }
 
-template <int... JB>
-__device__ __forceinline__ bool potf2_all(double (&T)[8][8], Potf2Ctx& x,
-                                          std::integer_sequence<int, JB...>) {
-  return (potf2_group<JB>(T, x) && ...);
-}
-
-template <int... JB>
-__device__ __forceinline__ void trtri_all(double (&T)[8][8], Potf2Ctx& x,
-                                          std::integer_sequence<int, JB...>) {
-  (trtri_group<JB>(T, x), ...);
+// all waves: S[r][c] -= sum_{q<16} L[r][c0+q] L[c][c0+q] over the lower
+// 16 x 16 tiles (ti >= tj) of rows and columns >= c0 + 16
+__device__ __forceinline__ void trailing_update(double* __restrict__ S, int c0, int wave, int lane) {
+  const int T = (NB - c0) / 16 - 1;
+  const int ntiles = T * (T + 1) / 2;
+  const int i16 = lane % 16, k4 = lane / 16;
+  for (int idx = wave; idx < ntiles; idx += 4) {
+    // idx -> (ti, tj), tj <= ti, rows of tiles in order
+    int ti = 0;
+    while ((ti + 1) * (ti + 2) / 2 <= idx) ti++;
+    const int tj = idx - ti * (ti + 1) / 2;
+    const int r0 = c0 + 16 + 16 * ti, q0 = c0 + 16 + 16 * tj;
+    d4 acc;
+#pragma unroll
+    for (int e = 0; e < 4; e++) acc[e] = S[(q0 + i16) * SLD + r0 + k4 + 4 * e];
+#pragma unroll
+    for (int s = 0; s < 4; s++) {
+      const double a = -S[(c0 + 4 * s + k4) * SLD + r0 + i16];   // A[i][k] = -L[r0 + i][c0 + 4s + k]
+      const double b = S[(c0 + 4 * s + k4) * SLD + q0 + i16];    // B[k][j] = L[q0 + j][c0 + 4s + k]
+      acc = MFMA64(a, b, acc);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; e++) S[(q0 + i16) * SLD + r0 + k4 + 4 * e] = acc[e];
+  }
 }
 
 __global__ __launch_bounds__(256) void k_potf2_inv(double* __restrict__ A, int64_t lda,
@@ -138,52 +116,136 @@ __global__ __launch_bounds__(256) void k_potf2_inv(double* __restrict__ A, int64
                                                     double* __restrict__ Ldiag,
                                                     double* __restrict__ Linv,
                                                     int* __restrict__ info) {
-  static_assert(NB == 128, "8 x 8 register tiles of 16");
-  __shared__ double buf[2][NB];
-  __shared__ double Lp[NB * (NB + 1) / 2];
+  static_assert(NB == 128, "8 panels of 16 columns; two row sets of 64 lanes");
+  // the block (factor phase), then the packed L and X (inverse phase) and
+  // one 16 x 16 scratch tile per wave
+  constexpr int S_DOUBLES = 2 * PK + 4 * 256 > NB * SLD ? 2 * PK + 4 * 256 : NB * SLD;
+  __shared__ double S[S_DOUBLES];
+  __shared__ int fail_s;
   if (*info != 0) return;
-  Potf2Ctx x;
-  x.buf = buf;
-  x.Lp = Lp;
-  x.t = threadIdx.x;
-  x.r = x.t % 16;
-  x.c = x.t / 16;
-  x.o = (int64_t)k * NB;
-  x.n = n;
-  x.fail = 0;
-  const int r = x.r, c = x.c;
-  const int64_t o = x.o;
-  double T[8][8];
-#pragma unroll
-  for (int b = 0; b < 8; b++)
-#pragma unroll
-    for (int a = 0; a < 8; a++) {
-      const int i = r + 16 * a, l = c + 16 * b;
-      T[a][b] = i >= l ? A[(o + i) + (o + l) * lda] : 0.0;
+  const int t = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(t / 64), lane = t % 64;
+  const int64_t o = (int64_t)k * NB;
+  // (unconditional loads, 16 in flight: the block's strict upper part is
+  // memory of the matrix too)
+#pragma unroll 16
+  for (int m = 0; m < NB * NB / 256; m++) {
+    const int idx = t + 256 * m, r = idx % NB, c = idx / NB;
+    const double v = A[(o + r) + (o + c) * lda];
+    S[c * SLD + r] = r >= c ? v : 0.0;
+  }
+  if (t == 0) fail_s = 0;
+  __syncthreads();
+  for (int p = 0; p < NB / 16; p++) {
+    const int c0 = 16 * p;
+    if (wave == 0) {
+      const int f = panel_factor(S, c0, lane, o, n);
+      if (f && lane == 0) fail_s = f;
     }
-  if (!potf2_all(T, x, std::make_integer_sequence<int, 8>{})) {
-    if (x.t == 0) *info = x.fail > 0 ? x.fail : (int)(o + 1);
+    __syncthreads();
+    if (fail_s) break;
+    if (c0 + 16 < NB) trailing_update(S, c0, wave, lane);
+    __syncthreads();
+  }
+  if (fail_s) {
+    if (t == 0) *info = fail_s;
     return;
   }
+  // L out; the lower triangle into registers for the packing
+  double lreg[(PK + 255) / 256];
 #pragma unroll
-  for (int b = 0; b < 8; b++)
+  for (int m = 0; m < (PK + 255) / 256; m++) lreg[m] = 0.0;
+#pragma unroll 16
+  for (int m = 0; m < NB * NB / 256; m++) {
+    const int idx = t + 256 * m, r = idx % NB, c = idx / NB;
+    const double sv = S[c * SLD + r];
+    const double v = r >= c ? sv : 0.0;
+    A[(o + r) + (o + c) * lda] = v;
+    Ldiag[(size_t)k * NB * NB + r + (size_t)c * NB] = v;
+  }
+  // packed position pi = t + 256 m  ->  (r, c): c from the column ends
+  // (pi grows with m, so c only moves forward)
+  {
+    int c = 0;
 #pragma unroll
-    for (int a = 0; a < 8; a++) {
-      const int i = r + 16 * a, l = c + 16 * b;
-      const double v = i >= l ? T[a][b] : 0.0;
-      A[(o + i) + (o + l) * lda] = v;
-      Ldiag[(size_t)k * NB * NB + i + (size_t)l * NB] = v;
-      T[a][b] = i == l ? 1.0 : 0.0;   // T becomes X, starting from the identity
+    for (int m = 0; m < (PK + 255) / 256; m++) {
+      const int pi = t + 256 * m;
+      if (pi < PK) {
+        while (pk(NB - 1, c) < pi) c++;
+        lreg[m] = S[c * SLD + c + (pi - pk(c, c))];
+      }
     }
-  __syncthreads();   // Lp complete, the buffers free
-  trtri_all(T, x, std::make_integer_sequence<int, 8>{});
+  }
+  __syncthreads();
+  double* __restrict__ Lp = S;               // packed L
+  double* __restrict__ Xp = S + PK;          // packed X = inv(L)
+  double* __restrict__ Tw = S + 2 * PK + 256 * wave;  // this wave's 16 x 16 scratch (row-major)
 #pragma unroll
-  for (int b = 0; b < 8; b++)
+  for (int m = 0; m < (PK + 255) / 256; m++) {
+    const int pi = t + 256 * m;
+    if (pi < PK) Lp[pi] = lreg[m];
+  }
+  __syncthreads();
+  // diagonal blocks: wave w takes blocks w and w + 4, lane j < 16 column j
+  const int i16 = lane % 16, k4 = lane / 16;
 #pragma unroll
-    for (int a = 0; a < 8; a++) {
-      const int i = r + 16 * a, l = c + 16 * b;
-      Linv[(size_t)k * NB * NB + i + (size_t)l * NB] = i >= l ? T[a][b] : 0.0;
+  for (int h = 0; h < 2; h++) {
+    const int b0 = 16 * (wave + 4 * h);
+    double x[16];
+#pragma unroll
+    for (int i = 0; i < 16; i++) {
+      double sacc = i == lane ? 1.0 : 0.0;
+#pragma unroll
+      for (int m = 0; m < i; m++) sacc = fma(-Lp[pk(b0 + i, b0 + m)], x[m], sacc);
+      x[i] = sacc * (1.0 / Lp[pk(b0 + i, b0 + i)]);
     }
+    if (lane < 16) {
+#pragma unroll
+      for (int i = 0; i < 16; i++)
+        if (i >= lane) Xp[pk(b0 + i, b0 + lane)] = x[i];
+    }
+  }
+  __syncthreads();
+  // off-diagonal blocks, block columns j = wave and 7 - wave
+  auto xload = [&](int r, int c) -> double { return r >= c ? Xp[pk(r, c)] : 0.0; };
+#pragma unroll
+  for (int h = 0; h < 2; h++) {
+    const int jb = h == 0 ? wave : NB / 16 - 1 - wave;
+    for (int ib = jb + 1; ib < NB / 16; ib++) {
+      // T = sum_{m=jb}^{ib-1} L_{ib,m} X_{m,jb}
+      d4 acc = (d4){0, 0, 0, 0};
+      for (int mb = jb; mb < ib; mb++) {
+#pragma unroll
+        for (int s = 0; s < 4; s++) {
+          const int kk = 16 * mb + 4 * s + k4;
+          const double a = Lp[pk(16 * ib + i16, kk)];   // A[i][k] = L[16 ib + i][kk]
+          const double b = xload(kk, 16 * jb + i16);    // B[k][j] = X[kk][16 jb + j]
+          acc = MFMA64(a, b, acc);
+        }
+      }
+      // T to the scratch tile (row-major), then X_ij = -X_ii T
+#pragma unroll
+      for (int e = 0; e < 4; e++) Tw[(k4 + 4 * e) * 16 + i16] = acc[e];
+      d4 acc2 = (d4){0, 0, 0, 0};
+#pragma unroll
+      for (int s = 0; s < 4; s++) {
+        const double a = -xload(16 * ib + i16, 16 * ib + 4 * s + k4);   // A[i][k] = -X_ii[i][4s + k]
+        const double b = Tw[(4 * s + k4) * 16 + i16];                    // B[k][j] = T[4s + k][j]
+        acc2 = MFMA64(a, b, acc2);
+      }
+#pragma unroll
+      for (int e = 0; e < 4; e++) Xp[pk(16 * ib + k4 + 4 * e, 16 * jb + i16)] = acc2[e];
+    }
+  }
+  __syncthreads();
+  // (pk(r, c) lies inside the packed X also for r < c: the reads are
+  // unconditional)
+#pragma unroll 16
+  for (int m = 0; m < NB * NB / 256; m++) {
+    const int idx = t + 256 * m, r = idx % NB, c = idx / NB;
+    const double xv = Xp[pk(r, c)];
+    Linv[(size_t)k * NB * NB + r + (size_t)c * NB] = r >= c ? xv : 0.0;
+  }
 }
 
 // Tile product on MFMA: a 128 x 128 tile computed by 4 waves (64 x 64 each)
