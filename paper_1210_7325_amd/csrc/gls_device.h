@@ -96,4 +96,87 @@ __device__ __forceinline__ double load_x(const TIn* __restrict__ X, int64_t ldx,
   return (row < n && col < ncols) ? (double)X[col * ldx + row] : 0.0;
 }
 
+// The diagonal step W_k = inv(L_kk) R_k of the 128-row solves (four wave
+// rows of two 16-row tiles), with R_k in LDS in the B-operand pair layout
+// and the row tiles dealt for balance:
+// 16-row tile t of inv(L_kk) R_k needs the first 2(t+1) k-step pairs (the
+// rest of its row of inv(L_kk) is zero), so wave row W takes tiles W and
+// NB/16 - 1 - W: NB/8 + 2 = 18 steps for every wave row (against up to
+// 2 NB/8 for wave row WR - 1 when it holds the last two tiles).  Same
+// products in the same order per element as diag_step.
+//
+// The wave row is a template parameter (the caller switches on it), so the
+// 18 steps unroll with static registers: the inv(L_kk) fragments are loaded
+// DIAG_PF steps ahead (the first ones by diag_prefetch, before R_k is
+// staged) and the R_k fragments one step ahead, and no step waits for a
+// load it has just issued (with a run-time trip count every step waited
+// for its own inv(L_kk) load from L2 and its LDS reads).
+constexpr int DIAG_PF = 4;
+
+template <int W>
+__device__ __forceinline__ const double* diag_a_ptr(const double* __restrict__ Li, int s) {
+  constexpr int NT = NB / 16, NA = 2 * (W + 1);
+  return s < NA ? Li + ((size_t)s * NT + W) * 128 : Li + ((size_t)(s - NA) * NT + (NT - 1 - W)) * 128;
+}
+
+template <int W>
+__device__ __forceinline__ void diag_prefetch(const double* __restrict__ LinvP, int k, int lane, d2 (&pa)[DIAG_PF]) {
+  const double* __restrict__ Li = LinvP + (size_t)k * NB * NB + lane * 2;
+#pragma unroll
+  for (int s = 0; s < DIAG_PF; s++) pa[s] = *reinterpret_cast<const d2*>(diag_a_ptr<W>(Li, s));
+}
+
+template <int CT, int CTS, int W>
+__device__ __forceinline__ void diag_step_dealt(const double* __restrict__ LinvP, int k,
+                                                const double* Rl, int wc_tile, int lane,
+                                                const d2 (&pa)[DIAG_PF], d4 (&w)[2][CT]) {
+  constexpr int NT = NB / 16, NA = 2 * (W + 1), NS = NA + 2 * (NT - W);
+  static_assert(NS > DIAG_PF, "prefetch depth");
+  const double* __restrict__ Li = LinvP + (size_t)k * NB * NB + lane * 2;
+  auto read_b = [&](int s, d2 (&b)[CT]) {
+    const int kp = s < NA ? s : s - NA;
+#pragma unroll
+    for (int ct = 0; ct < CT; ct++)
+      b[ct] = *reinterpret_cast<const d2*>(&Rl[((size_t)kp * CTS + wc_tile + ct) * 128 + lane * 2]);
+  };
+  d2 a[NS], b[2][CT];
+#pragma unroll
+  for (int s = 0; s < DIAG_PF; s++) a[s] = pa[s];
+#pragma unroll
+  for (int h = 0; h < 2; h++)
+#pragma unroll
+    for (int ct = 0; ct < CT; ct++) w[h][ct] = (d4){0, 0, 0, 0};
+  read_b(0, b[0]);
+#pragma unroll
+  for (int s = 0; s < NS; s++) {
+    if (s + DIAG_PF < NS) a[s + DIAG_PF] = *reinterpret_cast<const d2*>(diag_a_ptr<W>(Li, s + DIAG_PF));
+    if (s + 1 < NS) read_b(s + 1, b[(s + 1) % 2]);
+    const int h = s < NA ? 0 : 1;
+#pragma unroll
+    for (int ct = 0; ct < CT; ct++) {
+      w[h][ct] = MFMA64(a[s].x, b[s % 2][ct].x, w[h][ct]);
+      w[h][ct] = MFMA64(a[s].y, b[s % 2][ct].y, w[h][ct]);
+    }
+    // the loads first, then the MFMAs (left alone, the scheduler sinks the
+    // loads below the MFMAs to shorten their registers' lives, and every
+    // step then waits for its own reads)
+    if (s + DIAG_PF < NS) __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+    if (s + 1 < NS) __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
+    __builtin_amdgcn_sched_group_barrier(0x008, 2 * CT, 0);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// Runs STMT with the constant WROW = this wave's row (wave-uniform: a
+// scalar branch, no divergence).
+#define DIAG_BY_ROW(STMT)                        \
+  do {                                           \
+    switch (wr) {                                \
+      case 0: { constexpr int WROW = 0; STMT; } break; \
+      case 1: { constexpr int WROW = 1; STMT; } break; \
+      case 2: { constexpr int WROW = 2; STMT; } break; \
+      default: { constexpr int WROW = 3; STMT; } break; \
+    }                                            \
+  } while (0)
+
 }  // namespace gls

@@ -210,7 +210,8 @@ __global__ __launch_bounds__(64 * WR * WC) void k_trsm_mixed(const JobTable tab)
   double* __restrict__ Wslab = J.W + slab * (int64_t)K * NB * C;
   float* __restrict__ W32slab = J.W32 + slab * (int64_t)K * NB * C;
 
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  // the wave index is wave-uniform (kept in scalar registers)
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x % 64;
   const int wr = wave / WC, wc = wave % WC;
   const int64_t col_base = slab * C + wc * CW;
 
@@ -298,6 +299,10 @@ __global__ __launch_bounds__(64 * WR * WC) void k_trsm_mixed(const JobTable tab)
       }
     }
 
+    static_assert(WR == 4 && RT == 2, "the diagonal step deals two row tiles to each of four wave rows");
+    d2 pa[DIAG_PF];
+    DIAG_BY_ROW(diag_prefetch<WROW>(LinvP, k, lane, pa));
+
     // R_k = (x - s) - acc, to LDS in the FP64 B-operand pair layout: element
     // (row 4g + i) of the FP32 output goes to k-step (row0/4 + g), lane 16i + l%16;
     // padding rows take 0
@@ -316,45 +321,29 @@ __global__ __launch_bounds__(64 * WR * WC) void k_trsm_mixed(const JobTable tab)
     }
     __syncthreads();
 
-    d4 w64[RT][CT];
-#pragma unroll
-    for (int a = 0; a < RT; a++)
-#pragma unroll
-      for (int b = 0; b < CT; b++) w64[a][b] = (d4){0, 0, 0, 0};
-    const double* __restrict__ Li = LinvP + (size_t)k * NB * NB + (size_t)(wr * RT) * 128 + lane * 2;
-    const int kp_end = (wr * RW + RW) / 8;
-    for (int kp = 0; kp < kp_end; kp++) {
-      d2 a[RT], b[CT];
-#pragma unroll
-      for (int rt = 0; rt < RT; rt++)
-        a[rt] = *reinterpret_cast<const d2*>(Li + ((size_t)kp * (NB / 16) + rt) * 128);
-#pragma unroll
-      for (int ct = 0; ct < CT; ct++)
-        b[ct] = *reinterpret_cast<const d2*>(&Rl[((size_t)kp * CTS + wc * CT + ct) * 128 + lane * 2]);
-#pragma unroll
-      for (int rt = 0; rt < RT; rt++)
-#pragma unroll
-        for (int ct = 0; ct < CT; ct++) {
-          w64[rt][ct] = MFMA64(a[rt].x, b[ct].x, w64[rt][ct]);
-          w64[rt][ct] = MFMA64(a[rt].y, b[ct].y, w64[rt][ct]);
-        }
-    }
+    // W_k = inv(L_kk) R_k with the row tiles dealt (wave row wr takes 16-row
+    // tiles wr and NB/16 - 1 - wr; same products in the same order per
+    // element as the last-block kernel's)
+    d4 w64[2][CT];
+    DIAG_BY_ROW((diag_step_dealt<CT, CTS, WROW>(LinvP, k, Rl, wc * CT, lane, pa, w64)));
     // store W_k: FP64 pairs (identity per lane) and the FP32 quad copy
     // (element i of the FP64 output is k-step row0/4 + i, i.e. position i of
-    // quad row0/16, same lane)
+    // quad row0/16, same lane); typed global stores (generic ones would be
+    // flat stores, which later LDS waits would have to wait for too)
 #pragma unroll
-    for (int rt = 0; rt < RT; rt++) {
-      const int64_t row0 = (int64_t)k * NB + wr * RW + rt * 16;
+    for (int h = 0; h < 2; h++) {
+      const int tile = h == 0 ? wr : NB / 16 - 1 - wr;
+      const int64_t row0 = (int64_t)k * NB + 16 * tile;
       const int64_t ks0 = row0 / 4;
 #pragma unroll
       for (int ct = 0; ct < CT; ct++) {
 #pragma unroll
         for (int i = 0; i < 4; i += 2)
-          *reinterpret_cast<d2*>(Wslab + ((size_t)((ks0 + i) / 2) * CTS + wc * CT + ct) * 128 + lane * 2) =
-              (d2){w64[rt][ct][i], w64[rt][ct][i + 1]};
-        *reinterpret_cast<f4*>(W32slab + ((size_t)(row0 / 16) * CTS + wc * CT + ct) * 256 + lane * 4) =
-            (f4){(float)w64[rt][ct][0], (float)w64[rt][ct][1], (float)w64[rt][ct][2],
-                 (float)w64[rt][ct][3]};
+          *(__attribute__((address_space(1))) d2*)(Wslab + ((size_t)((ks0 + i) / 2) * CTS + wc * CT + ct) * 128 +
+                                                   lane * 2) = (d2){w64[h][ct][i], w64[h][ct][i + 1]};
+        *(__attribute__((address_space(1))) f4*)(W32slab + ((size_t)(row0 / 16) * CTS + wc * CT + ct) * 256 +
+                                                 lane * 4) =
+            (f4){(float)w64[h][ct][0], (float)w64[h][ct][1], (float)w64[h][ct][2], (float)w64[h][ct][3]};
       }
     }
     __threadfence_block();
