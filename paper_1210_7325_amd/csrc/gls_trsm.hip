@@ -45,11 +45,91 @@ __host__ __device__ inline bool last_block_split(int64_t n, int K, int RW) {
   return K > 1 && n - (int64_t)(K - 1) * NB <= RW;
 }
 
-// The last-block kernel always has four wave rows (NB / 4 rows each), so
-// that it sums the last block's GEMM in the same order whatever the slab
-// width (and whatever the main kernel's wave rows): results stay bitwise
-// independent of the width.
+// A split last block has at most LAST_RW real rows: one or two 16-row tiles.
 constexpr int LAST_RW = NB / 4;
+__host__ __device__ inline int last_block_tiles(int64_t n, int K) {
+  return n - (int64_t)(K - 1) * NB <= 16 ? 1 : 2;
+}
+
+// The off-diagonal sum of a split last block, grown as the walk produces
+// W: once blocks k0 .. k0 + NBLK - 1 are stored (and a barrier has made
+// them visible to the work-group), the wave adds their terms L_{K-1,j} W_j
+// to NR output tiles (row tiles lt0 .. lt0 + NR - 1 of block K-1, column
+// tile ct of the slab).  Each tile is one MFMA chain over the k-step pairs
+// in increasing order, the order of every other block's GEMM, so the
+// results are the same bits for every slab width.  Between calls a chain
+// sits in the slab's rows of block K-1 (unused until the last block's
+// diagonal step, which reads it from there), so the walk keeps no
+// registers for it; W_j comes from the slab, still in the caches, and the
+// strip of block K-1 from global memory, P pairs ahead.  This replaces a
+// second pass over the slab's whole W after the walk (10 MB per 128-column
+// slab from HBM).
+template <int CTS, int NR, int NBLK, int P>
+__device__ __forceinline__ void last_block_sum(const double* __restrict__ Lstrips, double* __restrict__ Wslab,
+                                               int K, int k0, int lt0, int ct, int lane) {
+  // P pairs in flight, each pinned where it is issued (left to the
+  // scheduler, the refills slid next to their use and three pairs in
+  // flight did not cover the latency of the strip's first touch)
+  constexpr int NPB = NB / 8, NKP = NBLK * NPB;
+  static_assert(P >= 1 && P <= NKP, "prefetch depth");
+  // Buffer loads and stores: a wave-uniform base (scalar registers), the
+  // lane's 16 bytes as the only vector offset and the step within the
+  // operand as a scalar offset, so that no per-lane 64-bit address lives
+  // across the walk (the walk's loop needs every vector register).
+  auto rsrc = [](const double* base) {
+    return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, 0x7fffffff, 0x00020000);
+  };
+  // two resources for the whole walk (the slab, the strip of block K-1);
+  // byte offsets within them (< 2^31: a slab is K NB C doubles, the strip's
+  // pairs up to block K-2 (K-1) NB^2 doubles)
+  const auto Lr = rsrc(Lstrips + strip_offset(K - 1));
+  const auto Wr = rsrc(Wslab);
+  const int la0 = (k0 * NPB * (NB / 16) + lt0) * 1024;
+  const int wb0 = (k0 * NPB * CTS + ct) * 1024;
+  const int ac0 = (((K - 1) * NPB + 2 * lt0) * CTS + ct) * 1024;
+  const int vo = lane * 16;
+  auto ld = [&](__amdgpu_buffer_rsrc_t r, int soff) {
+    return __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(r, vo, soff, 0));
+  };
+  d4 acc[NR];
+#pragma unroll
+  for (int r = 0; r < NR; r++) {
+    // (the first call starts the chain at zero; the load is issued anyway,
+    // so that no branch joins in front of the loop's waits)
+    const d2 lo = ld(Wr, ac0 + (2 * r) * CTS * 1024), hi = ld(Wr, ac0 + (2 * r + 1) * CTS * 1024);
+    acc[r] = k0 > 0 ? (d4){lo.x, lo.y, hi.x, hi.y} : (d4){0, 0, 0, 0};
+  }
+  d2 a[P][NR], b[P];
+#pragma unroll
+  for (int s = 0; s < P; s++) {
+#pragma unroll
+    for (int r = 0; r < NR; r++) a[s][r] = ld(Lr, la0 + (s * (NB / 16) + r) * 1024);
+    b[s] = ld(Wr, wb0 + s * CTS * 1024);
+  }
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int kp = 0; kp < NKP; kp++) {
+    const int s = kp % P;
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+      acc[r] = MFMA64(a[s][r].x, b[s].x, acc[r]);
+      acc[r] = MFMA64(a[s][r].y, b[s].y, acc[r]);
+    }
+    if (kp + P < NKP) {
+#pragma unroll
+      for (int r = 0; r < NR; r++) a[s][r] = ld(Lr, la0 + ((kp + P) * (NB / 16) + r) * 1024);
+      b[s] = ld(Wr, wb0 + (kp + P) * CTS * 1024);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < NR; r++)
+#pragma unroll
+    for (int h = 0; h < 2; h++)
+      __builtin_amdgcn_raw_buffer_store_b128(
+          __builtin_bit_cast(__attribute__((ext_vector_type(4))) unsigned, (d2){acc[r][2 * h], acc[r][2 * h + 1]}),
+          Wr, vo, ac0 + (2 * r + h) * CTS * 1024, 0);
+}
 
 template <int C, int G>
 constexpr int staged_ring_doubles(int S) { return S * G * (NB / 16 + C / 16) * 128; }
@@ -194,9 +274,13 @@ __global__ __launch_bounds__(64 * WR * WC) void k_trsm(const JobTable tab) {
   const int wr = wave / WC, wc = wave % WC;
   const int64_t col_base = slab * C + wc * CW;
 
-  // the last row block is left to k_trsm_last when all of its real rows
-  // lie in the first of its wave rows' tiles
-  const int Kmain = last_block_split(n, K, LAST_RW) ? K - 1 : K;
+  // when the last row block's real rows fit its first LAST_RW rows, the
+  // walk stops one block early, sums that block's GEMM as it goes
+  // (last_block_sum) and leaves its diagonal step to k_trsm_last
+  static_assert(2 * CTS <= WR * WC, "a wave for each output tile of the last block's sum");
+  const bool split = last_block_split(n, K, LAST_RW);
+  const int last_tiles = last_block_tiles(n, K);
+  const int Kmain = split ? K - 1 : K;
   for (int k = 0; k < Kmain; k++) {
     // this block's right-hand side, loaded early and held as loaded (it is
     // consumed after the GEMM).  When the wave's tile lies inside the matrix
@@ -330,6 +414,13 @@ __global__ __launch_bounds__(64 * WR * WC) void k_trsm(const JobTable tab) {
     }
     __threadfence_block();
     __syncthreads();
+    // W_k's terms of a split last block's sum: one output tile per wave
+    // (row tile wave / CTS, column tile wave % CTS); the other waves go on
+    // to the next block
+    if (split) {
+      const int lt0 = wave / CTS;
+      if (lt0 < last_tiles) last_block_sum<CTS, 1, 1, 4>(Lstrips, Wslab, K, k, lt0, wave % CTS, lane);
+    }
   }
 }
 
@@ -571,7 +662,12 @@ __global__ __launch_bounds__(64 * PAIR_WR * PAIR_WC) void k_trsm_pair(const JobT
   const int wr_rows = wr * RW, wc_tile = wc * CT;
   const int64_t col_base = slab * C + wc * CW;
 
-  const int Kmain = last_block_split(n, K, LAST_RW) ? K - 1 : K;
+  // a split last block: as in k_trsm, its sum grows pair by pair
+  // (last_block_sum, wave w: column tile w) and k_trsm_last does the rest
+  static_assert(CTS == WR * WC, "one column tile of the last block's sum per wave");
+  const bool split = last_block_split(n, K, LAST_RW);
+  const bool last_two_tiles = last_block_tiles(n, K) == 2;
+  const int Kmain = split ? K - 1 : K;
   for (int k = 0; k < Kmain; k += 2) {
     const bool two = k + 1 < Kmain;  // a lone last block: its partner's GEMM rows are discarded
     PHASE_STAMP(k / 2, 0);
@@ -661,25 +757,34 @@ __global__ __launch_bounds__(64 * PAIR_WR * PAIR_WC) void k_trsm_pair(const JobT
       store_w_dealt<CT, CTS>(Wslab, nullptr, k + 1, wr, wc_tile, lane, acc1);
       PHASE_STAMP(k / 2, 4);
     }
-    // the W stores are visible to the work-group's next copies, and every
-    // wave is done reading Rl before the next stage ring overwrites it
+    // the W stores are visible to the work-group's next copies (and to the
+    // last block's sum), and every wave is done reading Rl before the next
+    // stage ring overwrites it
     __threadfence_block();
     __syncthreads();
+    if (split) {
+      if (last_two_tiles) {
+        if (two) last_block_sum<CTS, 2, 2, 8>(Lstrips, Wslab, K, k, 0, wave, lane);
+        else last_block_sum<CTS, 2, 1, 8>(Lstrips, Wslab, K, k, 0, wave, lane);
+      } else {
+        if (two) last_block_sum<CTS, 1, 2, 16>(Lstrips, Wslab, K, k, 0, wave, lane);
+        else last_block_sum<CTS, 1, 1, 16>(Lstrips, Wslab, K, k, 0, wave, lane);
+      }
+    }
     PHASE_STAMP(k / 2, 5);
   }
 }
 
-// The last row block of every slab when last_block_split holds, after
-// k_trsm has solved the others (same grid, one work-group per slab).  Its
-// GEMM covers only the first RW rows (the only real ones), and the WR wave
-// rows share it: wave row w sums its quarter of the k NB/8 pairs for that
-// tile; the partial sums meet in LDS in a fixed order, then the diagonal
-// step W = inv(L_kk) R and the store run as in k_trsm (rows beyond the first
-// tile give W = 0, as padding must).  Without this, one wave row would do
-// the whole GEMM while the others multiply padding.
-template <int C, int WR, int WC, int D, typename TIn = int8_t>
-__global__ __launch_bounds__(64 * WR * WC) void k_trsm_last(const JobTable tab) {
-  constexpr int RW = NB / WR, RT = RW / 16;
+// The last row block of every slab when last_block_split holds, after the
+// walk (same grid, one work-group per slab): R = X - acc for its real row
+// tiles, acc being the off-diagonal sum that last_block_sum left in the
+// slab's rows of the block, zero for every other row; then the diagonal
+// step W = inv(L_kk) R and the store, as in k_trsm (rows past the real ones
+// come out zero, as padding must).  Four wave rows of NB / 4 rows, WC wave
+// columns.
+template <int C, int WC, typename TIn = int8_t>
+__global__ __launch_bounds__(256 * WC) void k_trsm_last(const JobTable tab) {
+  constexpr int WR = 4, RW = NB / WR, RT = RW / 16;
   constexpr int CW = C / WC, CT = CW / 16;
   constexpr int CTS = C / 16;
   constexpr int NPB = NB / 8;
@@ -689,8 +794,9 @@ __global__ __launch_bounds__(64 * WR * WC) void k_trsm_last(const JobTable tab) 
   while (jb + 1 < tab.njobs && (int64_t)blockIdx.x >= tab.j[jb + 1].slab0) jb++;
   const JobDesc& J = tab.j[jb];
   const int K = J.K;
-  if (!last_block_split(J.n, K, RW)) return;
+  if (!last_block_split(J.n, K, LAST_RW)) return;
   const int k = K - 1;
+  const int lt_end = last_block_tiles(J.n, K);
   const int64_t slab = (int64_t)blockIdx.x - J.slab0;
   const TIn* __restrict__ X = reinterpret_cast<const TIn*>(J.X);
   double* __restrict__ Wslab = J.W + slab * (int64_t)K * NB * C;
@@ -698,90 +804,35 @@ __global__ __launch_bounds__(64 * WR * WC) void k_trsm_last(const JobTable tab) 
   const int wr = wave / WC, wc = wave % WC;
   const int64_t col_base = slab * C + wc * CW;
 
-  // the first tile's right-hand side, added by the first wave row only
-  const double xs = wr == 0 ? 1.0 : 0.0;
-  double xv[RT][CT][4];
-#pragma unroll
-  for (int rt = 0; rt < RT; rt++)
-#pragma unroll
-    for (int ct = 0; ct < CT; ct++)
-#pragma unroll
-      for (int i = 0; i < 4; i++)
-        xv[rt][ct][i] = load_x<TIn>(X, J.ldx, (int64_t)k * NB + rt * 16 + lane / 16 + 4 * i,
-                                       col_base + ct * 16 + lane % 16, J.n, J.ncols);
-  d4 acc[RT][CT];
-#pragma unroll
-  for (int a = 0; a < RT; a++)
-#pragma unroll
-    for (int b = 0; b < CT; b++) acc[a][b] = (d4){0, 0, 0, 0};
-  const double* __restrict__ Ls = J.Lstrips + strip_offset(k) + lane * 2;  // row tile 0
-  const double* __restrict__ Wb = Wslab + (size_t)(wc * CT) * 128 + lane * 2;
-  const int nq = k * NPB / D;
-  const int p0 = nq * wr / WR * D, p1 = nq * (wr + 1) / WR * D;
-  if (p1 > p0) {
-    d2 a[D][RT], b[D][CT];
-#pragma unroll
-    for (int s = 0; s < D; s++) {
-#pragma unroll
-      for (int rt = 0; rt < RT; rt++)
-        a[s][rt] = *reinterpret_cast<const d2*>(Ls + ((size_t)(p0 + s) * (NB / 16) + rt) * 128);
-#pragma unroll
-      for (int ct = 0; ct < CT; ct++)
-        b[s][ct] = *reinterpret_cast<const d2*>(Wb + ((size_t)(p0 + s) * CTS + ct) * 128);
-      asm volatile("" ::: "memory");
-    }
-    for (int kp0 = p0; kp0 < p1; kp0 += D) {
-#pragma unroll
-      for (int s = 0; s < D; s++) {
-#pragma unroll
-        for (int rt = 0; rt < RT; rt++)
-#pragma unroll
-          for (int ct = 0; ct < CT; ct++) {
-            acc[rt][ct] = MFMA64(a[s][rt].x, b[s][ct].x, acc[rt][ct]);
-            acc[rt][ct] = MFMA64(a[s][rt].y, b[s][ct].y, acc[rt][ct]);
-          }
-        int nx = kp0 + s + D;
-        nx = nx < p1 ? nx : p1 - 1;
-#pragma unroll
-        for (int rt = 0; rt < RT; rt++)
-          a[s][rt] = *reinterpret_cast<const d2*>(Ls + ((size_t)nx * (NB / 16) + rt) * 128);
-#pragma unroll
-        for (int ct = 0; ct < CT; ct++)
-          b[s][ct] = *reinterpret_cast<const d2*>(Wb + ((size_t)nx * CTS + ct) * 128);
-        asm volatile("" ::: "memory");
-      }
-    }
-  }
-  // partial sums into this wave row's own rows of Rl; the first wave row's
-  // rows (one contiguous run of RW C doubles) then gather them
+  // R_k into LDS in the B-operand pair layout: the first wave row's real
+  // tiles x - acc, everything else zero (the sum of a tile past the real
+  // ones was never formed: its slab rows are not read into R)
 #pragma unroll
   for (int rt = 0; rt < RT; rt++) {
     const int rowl = wr * RW + rt * 16;
+    const bool real = wr == 0 && rt < lt_end;
 #pragma unroll
     for (int ct = 0; ct < CT; ct++)
 #pragma unroll
       for (int i = 0; i < 4; i += 2) {
         const int kp = (rowl / 4 + i) / 2;
+        const int64_t col = col_base + ct * 16 + lane % 16;
+        const int64_t row = (int64_t)k * NB + rowl + lane / 16 + 4 * i;
+        const d2 acc = *reinterpret_cast<const d2*>(
+            Wslab + ((size_t)(k * NPB + kp) * CTS + wc * CT + ct) * 128 + lane * 2);
+        const double x0 = load_x<TIn>(X, J.ldx, row, col, J.n, J.ncols);
+        const double x1 = load_x<TIn>(X, J.ldx, row + 4, col, J.n, J.ncols);
         *reinterpret_cast<d2*>(&Rl[((size_t)kp * CTS + wc * CT + ct) * 128 + lane * 2]) =
-            (d2){xs * xv[rt][ct][i] - acc[rt][ct][i], xs * xv[rt][ct][i + 1] - acc[rt][ct][i + 1]};
+            real ? (d2){x0 - acc.x, x1 - acc.y} : (d2){0.0, 0.0};
       }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < RW * C; i += 64 * WR * WC) {
-    double v = Rl[i];
-#pragma unroll
-    for (int w = 1; w < WR; w++) {
-      v += Rl[(size_t)w * RW * C + i];
-      Rl[(size_t)w * RW * C + i] = 0.0;
-    }
-    Rl[i] = v;
-  }
-  __syncthreads();
   // W_k = inv(L_kk) R_k and the store, as in k_trsm
+  d4 w[RT][CT];
 #pragma unroll
   for (int a = 0; a < RT; a++)
 #pragma unroll
-    for (int b = 0; b < CT; b++) acc[a][b] = (d4){0, 0, 0, 0};
+    for (int b = 0; b < CT; b++) w[a][b] = (d4){0, 0, 0, 0};
   const double* __restrict__ Li = J.LinvP + (size_t)k * NB * NB + (size_t)(wr * RT) * 128 + lane * 2;
   const int kp_end = (wr * RW + RW) / 8;
   for (int kp = 0; kp < kp_end; kp++) {
@@ -796,10 +847,12 @@ __global__ __launch_bounds__(64 * WR * WC) void k_trsm_last(const JobTable tab) 
     for (int rt = 0; rt < RT; rt++)
 #pragma unroll
       for (int ct = 0; ct < CT; ct++) {
-        acc[rt][ct] = MFMA64(a[rt].x, b[ct].x, acc[rt][ct]);
-        acc[rt][ct] = MFMA64(a[rt].y, b[ct].y, acc[rt][ct]);
+        w[rt][ct] = MFMA64(a[rt].x, b[ct].x, w[rt][ct]);
+        w[rt][ct] = MFMA64(a[rt].y, b[ct].y, w[rt][ct]);
       }
   }
+  // (the stores land on the acc tiles, which every wave read before the
+  // barrier above)
 #pragma unroll
   for (int rt = 0; rt < RT; rt++) {
     const int64_t ks0 = (int64_t)k * (NB / 4) + (wr * RW + rt * 16) / 4;
@@ -808,7 +861,7 @@ __global__ __launch_bounds__(64 * WR * WC) void k_trsm_last(const JobTable tab) 
 #pragma unroll
       for (int i = 0; i < 4; i += 2)
         *reinterpret_cast<d2*>(Wslab + ((size_t)((ks0 + i) / 2) * CTS + wc * CT + ct) * 128 + lane * 2) =
-            (d2){acc[rt][ct][i], acc[rt][ct][i + 1]};
+            (d2){w[rt][ct][i], w[rt][ct][i + 1]};
   }
 }
 
@@ -833,21 +886,21 @@ hipError_t launch_trsm_i8(const JobTable& tab, int64_t nslabs, int C, hipStream_
       // two waves per SIMD (one wave per SIMD issues FP64 MFMAs at about half
       // rate); a wave's pair of MFMAs is short, so 8 pairs are kept in flight
       k_trsm<16, 8, 1, 8, int8_t><<<(unsigned)nslabs, 512, 0, st>>>(tab);
-      if (last) k_trsm_last<16, 4, 1, TRSM_DEPTH><<<(unsigned)nslabs, 256, 0, st>>>(tab);
+      if (last) k_trsm_last<16, 1><<<(unsigned)nslabs, 256, 0, st>>>(tab);
       break;
     case 32:
       k_trsm<32, 4, 2, TRSM_DEPTH, int8_t><<<(unsigned)nslabs, 512, 0, st>>>(tab);
-      if (last) k_trsm_last<32, 4, 2, TRSM_DEPTH><<<(unsigned)nslabs, 512, 0, st>>>(tab);
+      if (last) k_trsm_last<32, 2><<<(unsigned)nslabs, 512, 0, st>>>(tab);
       break;
     case 64:
       k_trsm<64, 4, 2, TRSM_DEPTH, int8_t, 2, 4><<<(unsigned)nslabs, 512, 0, st>>>(tab);
-      if (last) k_trsm_last<64, 4, 2, TRSM_DEPTH><<<(unsigned)nslabs, 512, 0, st>>>(tab);
+      if (last) k_trsm_last<64, 2><<<(unsigned)nslabs, 512, 0, st>>>(tab);
       break;
     case 128:
       // row blocks in pairs: half the W re-reads of k_trsm (4.8% faster
       // than k_trsm's sixteen waves of 32 x 32 tiles, same bits)
       k_trsm_pair<128, int8_t><<<(unsigned)nslabs, 64 * PAIR_WR * PAIR_WC, 0, st>>>(tab);
-      if (last) k_trsm_last<128, 4, 2, 2><<<(unsigned)nslabs, 512, 0, st>>>(tab);
+      if (last) k_trsm_last<128, 2><<<(unsigned)nslabs, 512, 0, st>>>(tab);
       break;
     default: return hipErrorInvalidValue;
   }
@@ -863,15 +916,15 @@ hipError_t launch_trsm_f64(const JobTable& tab, int64_t nslabs, int C, hipStream
   switch (C) {
     case 16:
       k_trsm<16, 8, 1, 8, double><<<(unsigned)nslabs, 512, 0, st>>>(tab);
-      if (last) k_trsm_last<16, 4, 1, TRSM_DEPTH, double><<<(unsigned)nslabs, 256, 0, st>>>(tab);
+      if (last) k_trsm_last<16, 1, double><<<(unsigned)nslabs, 256, 0, st>>>(tab);
       break;
     case 64:
       k_trsm<64, 4, 2, TRSM_DEPTH, double, 2, 4><<<(unsigned)nslabs, 512, 0, st>>>(tab);
-      if (last) k_trsm_last<64, 4, 2, TRSM_DEPTH, double><<<(unsigned)nslabs, 512, 0, st>>>(tab);
+      if (last) k_trsm_last<64, 2, double><<<(unsigned)nslabs, 512, 0, st>>>(tab);
       break;
     case 128:
       k_trsm_pair<128, double><<<(unsigned)nslabs, 64 * PAIR_WR * PAIR_WC, 0, st>>>(tab);
-      if (last) k_trsm_last<128, 4, 2, 2, double><<<(unsigned)nslabs, 512, 0, st>>>(tab);
+      if (last) k_trsm_last<128, 2, double><<<(unsigned)nslabs, 512, 0, st>>>(tab);
       break;
     default: return hipErrorInvalidValue;
   }

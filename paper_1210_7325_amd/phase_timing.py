@@ -11,8 +11,8 @@ prints, from the stamps of thread 0 of every work-group:
   (128 FP64 flops per cycle and compute unit: four SIMDs, one
   16x16x4 MFMA of 2,048 flops per 64 cycles each), per range of pairs,
 * the share of the walk's cycles in the phases that are not the GEMM
-  (right-hand sides, the diagonal steps, the L_{k+1,k} W_k update, stores
-  and barriers).
+  (right-hand sides, the diagonal steps, the L_{k+1,k} W_k update, stores,
+  barriers and the terms of a split last block's sum).
 
     python -m paper_1210_7325_amd.phase_timing [--n 10000] [--cols 32768]
 """
@@ -103,13 +103,16 @@ def main() -> None:
         print(f"| GEMM: the same, pairs {a}-{b - 1} | {frac(slice(a, b)):.4f} |")
     tot = walk_cyc.mean()
     for i, name in enumerate(("GEMM", "right-hand side k, W_k and its store", "right-hand side k+1 and "
-                              "L_{k+1,k} W_k", "W_{k+1} and its store", "closing barrier")):
+                              "L_{k+1,k} W_k", "W_{k+1} and its store",
+                              "closing barrier and the last block's sum")):
         print(f"| cycles in {name} (share of the walk) | {ph[:, :, i].sum(1).mean()/tot:.4f} |")
     other = ph[:, :, 1:].sum(2).mean(0)
     # the non-GEMM phases' MFMA work: two diagonal steps (18 k-step pairs of
-    # 8 MFMAs per wave, 8 waves) and the update (16 k-step pairs x 16 MFMAs
-    # per wave)
-    nong_ideal = (2 * 18 * 8 * 8 + 16 * 16 * 8) * 2048 / 128.0
+    # 8 MFMAs per wave, 8 waves), the update (16 k-step pairs x 16 MFMAs per
+    # wave) and, with a split last block, its sum (two blocks of 16 k-step
+    # pairs x 2 MFMAs per 16-row tile and wave)
+    last_tiles = (1 if args.n - (K - 1) * 128 <= 16 else 2) if last_split else 0
+    nong_ideal = (2 * 18 * 8 * 8 + 16 * 16 * 8 + 2 * 16 * 2 * last_tiles * 8) * 2048 / 128.0
     print(f"| non-GEMM phases per pair (cycles, mean) / their MFMA work at the clock-limited rate | "
           f"{other.mean():.0f} / {nong_ideal:.0f} |")
     flops = float(args.n) ** 2 * min(args.cols, nslab * 128)
